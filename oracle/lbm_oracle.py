@@ -1,0 +1,545 @@
+"""Plain FP64 reference of the phase-change lattice-Boltzmann step.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Written with PyTorch
+CPU ops in float64 so that ``torch.autograd`` provides an independent
+reverse pass.  No blocking, fusion or reordering: each function is one step
+of the scheme in the paper's order and notation.
+
+Paper: Verdier, Kestener, Cartalade, "Performance portability of lattice
+Boltzmann methods for two-phase flows with phase change" (arXiv 2003.06342).
+
+Model (Sec. 2): conservative Allen-Cahn phase field phi (phi = 1 gas,
+phi = 0 liquid) with production m''' (Eqs. CAC_ChgtPhase, ProductionRate),
+incompressible Navier-Stokes with surface tension mu grad(phi) and buoyancy
+(Eqs. ConservMasse_ChgtPhase, ConvservQDM_ChgtPhase, Force_Total,
+SuperficialTensionForce, ChemicalPotential) and the heat equation with the
+latent-heat source (Eq. Temperature_ChgtPhase).
+
+Scheme (Sec. 3): three BGK populations f (NS), g (phi), s (T) in barred
+variables (Eqs. VariableChange_f, VariableChange_feq, LBE), equilibria
+Feq_NS_Incompr, Geq_Allen-Cahn_Eq, Seq_Temp with Gamma_i (Eq.
+FunctionGamma), sources Forcing, MicroProduction, SourceTerm_AllenCahn,
+Def_SourceTerms_Temp, moments Velocity, Pressure, Moment_Phi, Moment_Temp,
+directional-derivative gradient and Laplacian (Eqs. DerivDirec_Grad, Grad,
+DerivDirect_Laplacian, Laplacian), anti-bounce-back Dirichlet walls (Sec.
+3.3) and half-way bounce-back no-slip walls (Sec. 4.1.2, Poiseuille).
+
+Readings where the paper is silent or inconsistent (the GPU path takes the
+same ones):
+  R1  D2Q9 weights 4/9, 1/9, 1/36 (not printed); D3Q7 order +x,+y,+z,-x,-y,-z.
+  R2  every "3" of Eqs. Grad / Laplacian is 1/c_s^2 of the stencil lattice;
+      each population uses its own lattice's c_s^2 (1/3 D2Q9, D3Q19; 1/4
+      D3Q7, D2Q5).
+  R3  stencils use D2Q9 in 2-D and D3Q19 in 3-D whatever the g/s lattice.
+  R4  heat source S^s_i = -w_i (L/Cp) [d_t phi + div(u phi)] (sign fixed by
+      Eqs. Heat-Equation_dimensionless and Moment_Temp).
+  R5  buoyancy F_v = (rho(phi) - rho_l) g with g the gravity acceleration
+      vector (points down): upward on vapour, zero in liquid.
+  R6  the production term in Eq. Moment_Phi is lagged by one step (q_prev).
+  R7  d_t phi = phi^n - phi^{n-1} (0 at the first step).
+  R8  div(u phi) = sum_a of the a-th component of the Eq. Grad stencil applied
+      to u_a phi.
+  R9  n = grad(phi) / sqrt(|grad(phi)|^2 + eps^2), eps = 1e-9.
+  R10 alpha(phi) = (1 - phi) alpha_l + phi alpha_g, used for tau_s and in q.
+  R12 init: populations = equilibrium - S/2 at the initial fields with
+      d_t phi = 0 and div(u phi) from u0, so the moments return the inputs.
+  R13 half-way walls between node rows; stencil ghosts phi_g = 2 phi_w - phi_b
+      and u_g = -u_b; at an edge crossed by two walls the wall of the higher
+      axis (z over y over x) gives the anti-bounce-back value.
+  R17 the u of the current step enters Gamma_i of all three families.
+  R18 the pressure moment uses the current step's q.
+Parity unpinned beyond self-consistency and invariants: R6-R10, R13 as
+modelling choices, and chaotic trajectories after pinch-off.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+F64 = torch.float64
+
+
+# ---------------------------------------------------------------------------
+# Lattices (Sec. 3, lattice definitions; weights of D2Q9 and D2Q5: R1)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Lattice:
+    name: str
+    c: list          # Q tuples (cx, cy, cz)
+    w: list          # Q weights
+    cs2: float       # lattice speed of sound squared
+    opp: list        # index of -c_i
+
+    @property
+    def Q(self) -> int:
+        return len(self.w)
+
+
+def _make(name, c, w, cs2):
+    opp = [c.index(tuple(-v for v in ci)) for ci in c]
+    return Lattice(name, [tuple(ci) for ci in c], list(w), cs2, opp)
+
+
+def lattice(name: str) -> Lattice:
+    if name == "D2Q9":
+        c = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (-1, 0, 0), (0, -1, 0),
+             (1, 1, 0), (-1, 1, 0), (-1, -1, 0), (1, -1, 0)]
+        w = [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4
+        return _make(name, c, w, 1 / 3)
+    if name == "D2Q5":   # z-projection of D3Q7 (used by the z-invariance pin)
+        c = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (-1, 0, 0), (0, -1, 0)]
+        w = [1 / 2] + [1 / 8] * 4
+        return _make(name, c, w, 1 / 4)
+    if name == "D3Q7":
+        c = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1),
+             (-1, 0, 0), (0, -1, 0), (0, 0, -1)]
+        w = [1 / 4] + [1 / 8] * 6
+        return _make(name, c, w, 1 / 4)
+    if name == "D3Q19":
+        c = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1),
+             (-1, 0, 0), (0, -1, 0), (0, 0, -1),
+             (1, 1, 0), (-1, 1, 0), (1, -1, 0), (-1, -1, 0),
+             (1, 0, 1), (-1, 0, 1), (1, 0, -1), (-1, 0, -1),
+             (0, 1, 1), (0, -1, 1), (0, 1, -1), (0, -1, -1)]
+        w = [1 / 3] + [1 / 18] * 6 + [1 / 36] * 12
+        return _make(name, c, w, 1 / 3)
+    raise ValueError(name)
+
+
+# ---------------------------------------------------------------------------
+# State and intermediate fields
+# ---------------------------------------------------------------------------
+
+@dataclass
+class State:
+    """Post-streaming barred populations at time n plus the lagged scalars.
+
+    f: [Qf, nz, ny, nx] or None (NS off); g: [Qg, ...]; s: [Qs, ...] or None
+    (heat off); phi_prev = phi^{n-1} (R7); q_prev = q^{n-1} (R6)."""
+    f: Optional[torch.Tensor]
+    g: torch.Tensor
+    s: Optional[torch.Tensor]
+    phi_prev: torch.Tensor
+    q_prev: torch.Tensor
+
+
+@dataclass
+class Macros:
+    phi: torch.Tensor
+    grad_phi: list
+    lap_phi: torch.Tensor
+    n: list
+    mu: torch.Tensor
+    rho: torch.Tensor
+    grad_rho: list
+    F: list
+    u: list
+    dtphi: torch.Tensor
+    D: torch.Tensor
+    T: torch.Tensor
+    q: torch.Tensor
+    p: torch.Tensor
+    alpha: torch.Tensor
+    nu: torch.Tensor
+
+
+def _tensor_axis(a: int) -> int:
+    """Lattice axis a (0=x, 1=y, 2=z) -> dim of a [nz, ny, nx] tensor."""
+    return 2 - a
+
+
+class Model:
+    """Parameters plus the step of the scheme (all lattice units, dx = dt = 1).
+
+    ``prm`` is the plain parameter dict built by the workload module.
+    ``T_wall_faces`` optionally replaces the scalar wall temperature of a
+    face by a per-node face array: key (axis, side) -> tensor broadcastable
+    to [nz, ny, nx] (size 1 along ``axis``)."""
+
+    def __init__(self, prm: dict, T_wall_faces: Optional[dict] = None):
+        self.prm = prm
+        self.dim = int(prm["dim"])
+        self.shape = (int(prm["nz"]), int(prm["ny"]), int(prm["nx"]))
+        self.ns = bool(prm["ns"])
+        self.heat = bool(prm["heat"])
+        self.phase_change = bool(prm["phase_change"]) and self.heat
+        self.visc_linear = bool(prm["visc_linear"])
+        self.geq_cac = bool(prm["geq_cac"])
+        self.Lf = lattice(prm["lat_f"])
+        self.Lg = lattice(prm["lat_g"])
+        self.Ls = lattice(prm["lat_s"])
+        self.Lst = lattice("D2Q9" if self.dim == 2 else "D3Q19")   # R3
+        for key, v in (("nu_l", prm["nu_l"]), ("nu_g", prm["nu_g"]),
+                       ("mobility", prm["mobility"]), ("alpha_l", prm["alpha_l"]),
+                       ("alpha_g", prm["alpha_g"])):
+            if not v > 0:
+                raise ValueError(f"{key} must be > 0")
+        self.W = float(prm["W"])
+        self.sigma = float(prm["sigma"])
+        self.rho_l = float(prm["rho_l"])
+        self.rho_g = float(prm["rho_g"])
+        self.Lcp = float(prm["L_over_cp"])
+        self.T_sat = float(prm["T_sat"])
+        self.theta_I = float(prm["theta_I"])
+        self.A = float(prm["A_coef"])
+        self.M = float(prm["mobility"])
+        self.grav = [float(v) for v in prm["gravity"]]
+        self.body = [float(v) for v in prm.get("body_force", (0.0, 0.0, 0.0))]
+        self.eps = float(prm.get("eps_n", 1e-9))
+        # Eq. Def_K-H
+        self.K = 1.5 * self.W * self.sigma
+        self.H = 12.0 * self.sigma / self.W
+        self.wall = [prm["bc"][a] == "wall" for a in range(3)]
+        self.phi_w = [[float(prm["phi_wall"][a][s]) for s in range(2)] for a in range(3)]
+        self.T_w = [[torch.tensor(float(prm["T_wall"][a][s]), dtype=F64)
+                     for s in range(2)] for a in range(3)]
+        if T_wall_faces:
+            for (a, s), arr in T_wall_faces.items():
+                self.T_w[a][s] = torch.as_tensor(arr, dtype=F64)
+
+    # -- closures (Sec. 2) --------------------------------------------------
+
+    def density(self, phi):
+        """Eq. Density."""
+        return phi * self.rho_g + (1.0 - phi) * self.rho_l
+
+    def viscosity(self, phi):
+        """Eq. Viscosity (harmonic) or Eq. Visco_lin."""
+        nl, ng = self.prm["nu_l"], self.prm["nu_g"]
+        if self.visc_linear:
+            return (1.0 - phi) * nl + phi * ng
+        return nl * ng / (phi * nl + (1.0 - phi) * ng)
+
+    def diffusivity(self, phi):
+        """Thermal diffusivity interpolation (R10)."""
+        return (1.0 - phi) * self.prm["alpha_l"] + phi * self.prm["alpha_g"]
+
+    # -- ghosts and stencils (Sec. 3.4) ---------------------------------------
+
+    def ghost_pad(self, v, kind: str):
+        """Pad a [nz, ny, nx] field by one ghost layer on every axis.
+
+        Periodic axes wrap; wall axes use the half-way mirror (R13):
+        'phi' -> 2 phi_w - v_b, 'anti' -> -v_b (no-slip velocity)."""
+        out = v
+        for a in range(3):
+            d = _tensor_axis(a)
+            n = out.shape[d]
+            first = out.narrow(d, 0, 1)
+            last = out.narrow(d, n - 1, 1)
+            if not self.wall[a]:
+                lo, hi = last, first
+            elif kind == "phi":
+                lo = 2.0 * self.phi_w[a][0] - first
+                hi = 2.0 * self.phi_w[a][1] - last
+            elif kind == "anti":
+                lo, hi = -first, -last
+            else:
+                raise ValueError(kind)
+            out = torch.cat([lo, out, hi], dim=d)
+        return out
+
+    def _shift(self, padded, e):
+        """padded value at x + e for every interior node x."""
+        nz, ny, nx = self.shape
+        ex, ey, ez = e
+        return padded[1 + ez:1 + ez + nz, 1 + ey:1 + ey + ny, 1 + ex:1 + ex + nx]
+
+    def grad(self, padded):
+        """Eqs. DerivDirec_Grad and Grad: (1/c_s^2) sum_i w_i e_i [v(x+e_i) -
+        v(x-e_i)] / 2 over the stencil lattice (R2, R3)."""
+        L = self.Lst
+        out = [torch.zeros(self.shape, dtype=F64) for _ in range(3)]
+        for i in range(1, L.Q):
+            e = L.c[i]
+            dd = 0.5 * (self._shift(padded, e) - self._shift(padded, tuple(-x for x in e)))
+            for a in range(3):
+                if e[a] != 0:
+                    out[a] = out[a] + L.w[i] * e[a] * dd
+        return [o / L.cs2 for o in out]
+
+    def laplacian(self, padded, centre):
+        """Eqs. DerivDirect_Laplacian and Laplacian."""
+        L = self.Lst
+        out = torch.zeros(self.shape, dtype=F64)
+        for i in range(1, L.Q):
+            e = L.c[i]
+            out = out + L.w[i] * (self._shift(padded, e) - 2.0 * centre
+                                  + self._shift(padded, tuple(-x for x in e)))
+        return out / L.cs2
+
+    # -- moments and closures at the current populations (S1-S7) -------------
+
+    def forces(self, phi, grad_phi, lap_phi):
+        """Chemical potential (Eq. ChemicalPotential with Eq. Def_K-H), surface
+        tension mu grad(phi) (Eq. SuperficialTensionForce) and buoyancy (R5);
+        F_tot = F_s + F_v (Eq. Force_Total) plus an optional uniform body
+        force (the pressure-gradient surrogate of the Poiseuille case)."""
+        mu = 4.0 * self.H * phi * (phi - 1.0) * (phi - 0.5) - self.K * lap_phi
+        rho = self.density(phi)
+        F = [mu * grad_phi[a] + (rho - self.rho_l) * self.grav[a] + self.body[a]
+             for a in range(3)]
+        return mu, rho, F
+
+    def divergence(self, u, phi_padded):
+        """div(u phi) with the central directional-derivative stencil (R8)."""
+        D = torch.zeros(self.shape, dtype=F64)
+        for a in range(3):
+            prod = self.ghost_pad(u[a], "anti") * phi_padded
+            D = D + self.grad(prod)[a]
+        return D
+
+    def production(self, phi, T, alpha):
+        """q = m'''/rho_g of Eq. ProductionRate with theta = (Cp/L)(T - T_sat)."""
+        if not self.phase_change:
+            return torch.zeros_like(phi)
+        theta = (T - self.T_sat) / self.Lcp
+        return -(4.0 * alpha / (self.A * self.W * self.W)) * (self.theta_I - theta) \
+            * phi * (1.0 - phi)
+
+    def macros(self, st: State, u_prescribed=None) -> Macros:
+        # S1: Eq. Moment_Phi, production lagged (R6)
+        phi = st.g.sum(0) + 0.5 * st.q_prev
+        # S2: stencils and closures
+        P = self.ghost_pad(phi, "phi")
+        gphi = self.grad(P)
+        lphi = self.laplacian(P, phi)
+        norm = torch.sqrt(gphi[0] ** 2 + gphi[1] ** 2 + gphi[2] ** 2 + self.eps ** 2)
+        n = [gphi[a] / norm for a in range(3)]
+        mu, rho, F = self.forces(phi, gphi, lphi)
+        grho = [(self.rho_g - self.rho_l) * gphi[a] for a in range(3)]
+        # S3: Eq. Velocity
+        if self.ns:
+            Lf = self.Lf
+            u = []
+            for a in range(3):
+                m1 = sum(st.f[i] * Lf.c[i][a] for i in range(Lf.Q) if Lf.c[i][a] != 0)
+                if isinstance(m1, int):
+                    m1 = torch.zeros(self.shape, dtype=F64)
+                u.append((m1 / Lf.cs2 + 0.5 * F[a]) / rho)
+        elif u_prescribed is not None:
+            u = [torch.as_tensor(u_prescribed[a], dtype=F64) * torch.ones(self.shape, dtype=F64)
+                 for a in range(3)]
+        else:
+            u = [torch.zeros(self.shape, dtype=F64) for _ in range(3)]
+        # S4: time derivative (R7) and divergence (R8)
+        dtphi = phi - st.phi_prev
+        alpha = self.diffusivity(phi)
+        if self.heat:
+            D = self.divergence(u, P)
+            # S5: Eq. Moment_Temp
+            T = st.s.sum(0) - 0.5 * self.Lcp * (dtphi + D)
+        else:
+            D = torch.zeros(self.shape, dtype=F64)
+            T = torch.zeros(self.shape, dtype=F64)
+        # S6: Eq. ProductionRate
+        q = self.production(phi, T, alpha)
+        # S7: Eq. Pressure (R18)
+        if self.ns:
+            cs2 = self.Lf.cs2
+            mdot = self.rho_g * q
+            udr = sum(u[a] * grho[a] for a in range(3))
+            p = st.f.sum(0) + 0.5 * (cs2 * udr + rho * cs2 * mdot
+                                     * (1.0 / self.rho_g - 1.0 / self.rho_l))
+        else:
+            p = torch.zeros(self.shape, dtype=F64)
+        return Macros(phi, gphi, lphi, n, mu, rho, grho, F, u, dtphi, D, T, q, p,
+                      alpha, self.viscosity(phi))
+
+    # -- equilibria, sources, collision (S8-S10) --------------------------------
+
+    def gamma(self, L: Lattice, u):
+        """Eq. FunctionGamma for every direction: list of Q tensors."""
+        uu = u[0] ** 2 + u[1] ** 2 + u[2] ** 2
+        out = []
+        for i in range(L.Q):
+            cu = sum(L.c[i][a] * u[a] for a in range(3) if L.c[i][a] != 0)
+            if isinstance(cu, int):
+                cu = torch.zeros(self.shape, dtype=F64)
+            out.append(L.w[i] * (1.0 + cu / L.cs2 + cu * cu / (2.0 * L.cs2 ** 2)
+                                 - uu / (2.0 * L.cs2)))
+        return out
+
+    def f_terms(self, m: Macros):
+        """Eq. Feq_NS_Incompr and source S^f = F^f + P^f (Eqs. Forcing,
+        MicroProduction).  Returns (feq, S) lists."""
+        L = self.Lf
+        Gm = self.gamma(L, m.u)
+        cs2 = L.cs2
+        prod = m.rho * cs2 * self.rho_g * m.q * (1.0 / self.rho_g - 1.0 / self.rho_l)
+        feq, S = [], []
+        for i in range(L.Q):
+            feq.append(L.w[i] * m.p + m.rho * cs2 * (Gm[i] - L.w[i]))
+            Ff = 0.0
+            for a in range(3):
+                Ff = Ff + (L.c[i][a] - m.u[a]) * ((Gm[i] - L.w[i]) * cs2 * m.grad_rho[a]
+                                                  + Gm[i] * m.F[a])
+            S.append(Ff + L.w[i] * prod)
+        return feq, S
+
+    def g_terms(self, m: Macros):
+        """Eq. Geq_Allen-Cahn_Eq with S^g = F^g + P^g (Eq. SourceTerm_AllenCahn),
+        or, with ``geq_cac``, the equivalent Eq. Geq_AC-1 with only P^g."""
+        L = self.Lg
+        Gm = self.gamma(L, m.u)
+        k = (4.0 / self.W) * m.phi * (1.0 - m.phi)
+        geq, S = [], []
+        for i in range(L.Q):
+            cn = sum(L.c[i][a] * m.n[a] for a in range(3) if L.c[i][a] != 0)
+            Fg = k * L.w[i] * cn
+            Pg = L.w[i] * m.q
+            if self.geq_cac:
+                geq.append(m.phi * Gm[i] + self.M * Fg / L.cs2)
+                S.append(Pg + 0.0 * m.phi)
+            else:
+                geq.append(m.phi * Gm[i])
+                S.append(Fg + Pg)
+        return geq, S
+
+    def s_terms(self, m: Macros):
+        """Eq. Seq_Temp with S^s_i = -w_i (L/Cp)[d_t phi + div(u phi)] (R4)."""
+        L = self.Ls
+        Gm = self.gamma(L, m.u)
+        src = -self.Lcp * (m.dtphi + m.D)
+        return [m.T * Gm[i] for i in range(L.Q)], [L.w[i] * src for i in range(L.Q)]
+
+    @staticmethod
+    def bgk(pop_i, eq_i, S_i, omega):
+        """Eq. LBE with Eq. VariableChange_feq: bar-eq = eq - S/2."""
+        return pop_i - omega * (pop_i - (eq_i - 0.5 * S_i)) + S_i
+
+    def collide(self, st: State, m: Macros):
+        out_f = out_s = None
+        if self.ns:
+            feq, S = self.f_terms(m)
+            om = 1.0 / (m.nu / self.Lf.cs2 + 0.5)          # tau_f = nu/c_s^2
+            out_f = torch.stack([self.bgk(st.f[i], feq[i], S[i], om)
+                                 for i in range(self.Lf.Q)])
+        geq, S = self.g_terms(m)
+        om_g = 1.0 / (self.M / self.Lg.cs2 + 0.5)            # M = tau_g c_s^2
+        out_g = torch.stack([self.bgk(st.g[i], geq[i], S[i], om_g)
+                             for i in range(self.Lg.Q)])
+        if self.heat:
+            seq, S = self.s_terms(m)
+            om_s = 1.0 / (m.alpha / self.Ls.cs2 + 0.5)      # alpha = tau_s c_s^2
+            out_s = torch.stack([self.bgk(st.s[i], seq[i], S[i], om_s)
+                                 for i in range(self.Ls.Q)])
+        return out_f, out_g, out_s
+
+    # -- streaming with walls (S11) ---------------------------------------------
+
+    def _boundary_mask(self, a: int, side: int):
+        d = _tensor_axis(a)
+        n = self.shape[d]
+        idx = torch.arange(n)
+        m = (idx == 0) if side == 0 else (idx == n - 1)
+        shape = [1, 1, 1]
+        shape[d] = n
+        return m.reshape(shape)
+
+    def stream(self, post, L: Lattice, kind: str, wall_val=None):
+        """Pull streaming new_i(x) = post_i(x - c_i) (periodic roll); at a wall
+        the link reflects: bounce-back new_i = post_{i'} ('bb') or
+        anti-bounce-back new_i = -post_{i'} + 2 w_i V_w ('abb', Sec. 3.3)."""
+        out = []
+        for i in range(L.Q):
+            c = L.c[i]
+            v = torch.roll(post[i], shifts=(c[2], c[1], c[0]), dims=(0, 1, 2))
+            for a in range(3):          # higher axis applied last wins (R13)
+                if not self.wall[a] or c[a] == 0:
+                    continue
+                side = 0 if c[a] > 0 else 1
+                mask = self._boundary_mask(a, side)
+                if kind == "bb":
+                    repl = post[L.opp[i]]
+                else:
+                    repl = -post[L.opp[i]] + 2.0 * L.w[i] * wall_val[a][side]
+                v = torch.where(mask, repl, v)
+            out.append(v)
+        return torch.stack(out)
+
+    # -- one time step ------------------------------------------------------------
+
+    def step(self, st: State, u_prescribed=None) -> State:
+        m = self.macros(st, u_prescribed)
+        pf, pg, ps = self.collide(st, m)
+        phiw = [[torch.tensor(v, dtype=F64) for v in side] for side in self.phi_w]
+        nf = self.stream(pf, self.Lf, "bb") if self.ns else None
+        ng = self.stream(pg, self.Lg, "abb", phiw)
+        ns_ = self.stream(ps, self.Ls, "abb", self.T_w) if self.heat else None
+        return State(nf, ng, ns_, m.phi, m.q)
+
+    def run(self, st: State, nsteps: int, u_prescribed=None) -> State:
+        for _ in range(nsteps):
+            st = self.step(st, u_prescribed)
+        return st
+
+    # -- initialisation (R12) ---------------------------------------------------
+
+    def init(self, phi0, T0=None, u0=None, p0=None) -> State:
+        phi = torch.as_tensor(phi0, dtype=F64).reshape(self.shape)
+        T = (torch.zeros(self.shape, dtype=F64) if (T0 is None or not self.heat)
+             else torch.as_tensor(T0, dtype=F64).reshape(self.shape))
+        u = ([torch.zeros(self.shape, dtype=F64) for _ in range(3)] if u0 is None
+             else [torch.as_tensor(u0[a], dtype=F64).reshape(self.shape) for a in range(3)])
+        if not self.ns and u0 is None:
+            u = [torch.zeros(self.shape, dtype=F64) for _ in range(3)]
+        p = (torch.zeros(self.shape, dtype=F64) if p0 is None
+             else torch.as_tensor(p0, dtype=F64).reshape(self.shape))
+        P = self.ghost_pad(phi, "phi")
+        gphi = self.grad(P)
+        lphi = self.laplacian(P, phi)
+        norm = torch.sqrt(gphi[0] ** 2 + gphi[1] ** 2 + gphi[2] ** 2 + self.eps ** 2)
+        n = [gphi[a] / norm for a in range(3)]
+        mu, rho, F = self.forces(phi, gphi, lphi)
+        grho = [(self.rho_g - self.rho_l) * gphi[a] for a in range(3)]
+        alpha = self.diffusivity(phi)
+        D = self.divergence(u, P) if self.heat else torch.zeros(self.shape, dtype=F64)
+        q = self.production(phi, T, alpha) if self.heat else torch.zeros(self.shape, dtype=F64)
+        zero = torch.zeros(self.shape, dtype=F64)
+        m = Macros(phi, gphi, lphi, n, mu, rho, grho, F, u, zero, D, T, q, p, alpha,
+                   self.viscosity(phi))
+        f = g = s = None
+        if self.ns:
+            feq, S = self.f_terms(m)
+            f = torch.stack([feq[i] - 0.5 * S[i] for i in range(self.Lf.Q)])
+        geq, S = self.g_terms(m)
+        g = torch.stack([geq[i] - 0.5 * S[i] for i in range(self.Lg.Q)])
+        if self.heat:
+            seq, S = self.s_terms(m)
+            s = torch.stack([seq[i] - 0.5 * S[i] for i in range(self.Ls.Q)])
+        return State(f, g, s, phi.clone(), q)
+
+    # -- outputs ----------------------------------------------------------------
+
+    def fields(self, st: State, u_prescribed=None) -> dict:
+        """phi, p, u, T from the current populations (S1-S7)."""
+        m = self.macros(st, u_prescribed)
+        return dict(phi=m.phi, p=m.p, ux=m.u[0], uy=m.u[1], uz=m.u[2], T=m.T)
+
+    def diagnostics(self, st: State) -> dict:
+        """FP64 sums: Phi = sum phi, E = sum T + (L/Cp)(Phi + Phi_prev)/2,
+        vapour fraction Phi/N, max|u|."""
+        m = self.macros(st)
+        Phi = m.phi.sum()
+        Phi_prev = st.phi_prev.sum()
+        E = m.T.sum() + self.Lcp * 0.5 * (Phi + Phi_prev)
+        umag = torch.sqrt(m.u[0] ** 2 + m.u[1] ** 2 + m.u[2] ** 2)
+        N = m.phi.numel()
+        return dict(mass=float(Phi), enthalpy=float(E), vapour=float(Phi) / N,
+                    umax=float(umag.max()))
+
+
+def relative_l2(x, ref, about_mean: bool = False) -> float:
+    x = torch.as_tensor(x, dtype=F64)
+    ref = torch.as_tensor(ref, dtype=F64)
+    if about_mean:
+        x = x - x.mean()
+        ref = ref - ref.mean()
+    den = float(torch.linalg.vector_norm(ref))
+    num = float(torch.linalg.vector_norm(x - ref))
+    return num / den if den > 0 else num
