@@ -1,0 +1,178 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) phase-change lattice-Boltzmann step.
+ *
+ * The method is the three-population BGK scheme of Verdier, Kestener and
+ * Cartalade (arXiv 2003.06342): a conservative Allen-Cahn phase field phi
+ * with interface mass production (Sec. 2.1, Eqs. CAC_ChgtPhase and
+ * ProductionRate; LB scheme Sec. 3.2), incompressible Navier-Stokes with
+ * surface tension mu*grad(phi) and buoyancy (Eqs. ConservMasse_ChgtPhase,
+ * ConvservQDM_ChgtPhase, Force_Total, ChemicalPotential; LB scheme Sec.
+ * 3.1) and the heat equation with latent heat (Eq. Temperature_ChgtPhase;
+ * LB scheme Sec. 3.3), coupled by the isotropic gradient and Laplacian of
+ * Sec. 3.4.  All quantities are in lattice units (dx = dt = 1).
+ *
+ * Conventions
+ *   - Field arrays are C-ordered [nz][ny][nx] (nz = 1 in 2-D), x fastest.
+ *     Node (i, j, k) has its centre at (i+1/2, j+1/2, k+1/2); a wall axis
+ *     has half-way walls on the planes 0 and n.
+ *   - Every pointer argument named dev_* or documented as "device" is a HIP
+ *     device pointer on the context's device.  Host pointers are marked.
+ *   - Ownership: the caller owns every buffer.  The library never allocates
+ *     device memory: it borrows the workspace given to lbm_create for the
+ *     lifetime of the context and field/state pointers for the duration of
+ *     one call.  The context object itself is host memory owned by the
+ *     library (freed by lbm_destroy).
+ *   - Calls are asynchronous and ordered on the stream given to lbm_create
+ *     unless documented as synchronising.  A context must not be used from
+ *     two threads at once.
+ *   - Errors: every call returns an lbm_status; nothing throws across the
+ *     ABI.  lbm_last_error() gives a message for the last failure on the
+ *     calling thread.  Faults of earlier asynchronous work surface as
+ *     LBM_E_HIP at the next synchronising call.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+typedef int32_t lbm_status;
+
+#define LBM_OK 0
+#define LBM_E_INVAL (-1)        /* invalid argument or parameter set        */
+#define LBM_E_NOMEM (-2)        /* a caller buffer is too small             */
+#define LBM_E_HIP (-3)          /* the HIP runtime reported an error        */
+#define LBM_E_STATE (-4)        /* call made in the wrong order             */
+#define LBM_E_UNSTABLE (-5)     /* non-finite values in the diagnostics     */
+#define LBM_E_UNSUPPORTED (-6)  /* valid but not built (lattice/BC combo)   */
+
+/* Lattices (Sec. 3): D2Q9 in 2-D for f, g and s; in 3-D D3Q19 for f and
+ * D3Q7 for g and s.  Stencils use D2Q9 in 2-D and D3Q19 in 3-D. */
+enum { LBM_D2Q9 = 9, LBM_D3Q7 = 7, LBM_D3Q19 = 19 };
+
+/* Population storage.  F16_DEV / BF16_DEV store each population as the
+ * 16-bit float (value - w_i * ref) * 2^k with a per-family reference and
+ * power-of-two scale; arithmetic is FP32.  Lagged scalars stay FP32. */
+enum { LBM_ST_F64 = 0, LBM_ST_F32 = 1, LBM_ST_F16_DEV = 2, LBM_ST_BF16_DEV = 3 };
+
+/* Per-axis boundary: periodic, or half-way walls on both faces.  A wall is
+ * a no-slip bounce-back wall for f (Sec. 4.1.2) and an anti-bounce-back
+ * Dirichlet wall for g and s (Sec. 3.3) with the face values phi_wall and
+ * T_wall (T_wall may be set per node with lbm_set_wall_T). */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 };
+
+/* Model switches. */
+enum {
+  LBM_NS = 1,            /* evolve f (else u = 0, p = 0)                    */
+  LBM_HEAT = 2,          /* evolve s (else T = 0 and no phase change)       */
+  LBM_PHASE_CHANGE = 4,  /* production q = m'''/rho_g of Eq. ProductionRate */
+  LBM_VISC_LINEAR = 8,   /* Eq. Visco_lin instead of the harmonic Eq. Viscosity */
+  LBM_GEQ_CAC = 16       /* CAC equilibrium form of Eq. Geq_AC-1            */
+};
+
+/* dtype of caller field arrays */
+enum { LBM_DT_F32 = 0, LBM_DT_F64 = 1 };
+
+/* Field selection bits of lbm_get_fields; output planes follow bit order. */
+enum {
+  LBM_FIELD_PHI = 1, LBM_FIELD_P = 2, LBM_FIELD_UX = 4, LBM_FIELD_UY = 8,
+  LBM_FIELD_UZ = 16, LBM_FIELD_T = 32
+};
+
+typedef struct {
+  int32_t dim;                   /* 2 or 3                                     */
+  int32_t nx, ny, nz;            /* nodes per axis, nz = 1 in 2-D              */
+  int32_t lat_f, lat_g, lat_s;   /* LBM_D2Q9 (2-D) or LBM_D3Q19/LBM_D3Q7 (3-D) */
+  int32_t storage;               /* LBM_ST_*                                   */
+  uint32_t flags;                /* LBM_NS | LBM_HEAT | ...                    */
+  /* transport: nu = tau_f c_s^2, M = tau_g c_s^2, alpha = tau_s c_s^2
+   * (Sec. 3.1-3.3); liquid is phi = 0, vapour phi = 1                      */
+  double nu_l, nu_g, mobility, alpha_l, alpha_g;
+  /* interface width W, surface tension sigma (Eq. Def_K-H), densities      */
+  double W, sigma, rho_l, rho_g;
+  /* L/Cp, saturation temperature, interface temperature theta_I and the
+   * coefficient A of Eq. ProductionRate (0 selects 10/48, App. B)           */
+  double L_over_cp, T_sat, theta_I, A_coef;
+  double gravity[3];             /* acceleration vector; buoyancy (rho - rho_l) g */
+  double body_force[3];          /* uniform force density added to F_tot     */
+  int32_t bc[3];                 /* LBM_BC_* per axis x, y, z                 */
+  double phi_wall[3][2];         /* [axis][lo, hi] anti-bounce-back phi       */
+  double T_wall[3][2];           /* [axis][lo, hi] anti-bounce-back T         */
+  double eps_n;                  /* regularisation of n = grad phi / |grad phi| (0 -> 1e-9) */
+} lbm_params;
+
+/* Bytes of device workspace lbm_create needs for these parameters
+ * (populations A and B, lagged phi and q, wall rows, reduction scratch).
+ * Returns LBM_E_INVAL / LBM_E_UNSUPPORTED for parameter sets that
+ * lbm_create would reject. */
+lbm_status lbm_workspace_size(const lbm_params* prm, size_t* bytes);
+
+/* Validate the parameters (tau > 0, omega = 1/(tau + 1/2) < 2 for the
+ * extreme phases, rho > 0, W > 0, lattice/dimension pairs) and build a
+ * context that uses `dev_workspace` (>= lbm_workspace_size bytes, 256-byte
+ * aligned, owned by the caller) and launches on `hip_stream` (a
+ * hipStream_t; NULL = the null stream).  *out is NULL on failure. */
+lbm_status lbm_create(const lbm_params* prm, void* dev_workspace, size_t bytes,
+                      void* hip_stream, lbm_ctx** out);
+
+/* Initialise the populations from phi0, T0 (device arrays [nz][ny][nx]) and
+ * the optional u0 ([3][nz][ny][nx], NULL = 0) and p0 (NULL = 0): every
+ * population is set to its equilibrium minus half its source at these
+ * fields, so that the moments of the first step return them exactly.
+ * T0 is ignored without LBM_HEAT.  dtype = LBM_DT_F32 or LBM_DT_F64. */
+lbm_status lbm_init_fields(lbm_ctx* ctx, const void* phi0, const void* T0,
+                           const void* u0, const void* p0, int32_t dtype);
+
+/* Per-node wall temperature on face (axis, side): a device array over the
+ * other two axes in [..][..] C order (2-D y wall: nx values; 3-D z wall:
+ * [ny][nx]).  Takes effect for the following steps. */
+lbm_status lbm_set_wall_T(lbm_ctx* ctx, int32_t axis, int32_t side,
+                          const void* dev_face, int32_t dtype);
+
+/* Advance nsteps time steps (asynchronous, stream-ordered).  Each step is
+ * one fused pass: pull streaming with wall links, moments, stencils,
+ * closures, equilibria, sources and BGK collision of f, g and s. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
+
+/* Write the macroscopic fields selected by `mask` (LBM_FIELD_* bits) at the
+ * current populations into dev_out, one [nz][ny][nx] plane per selected
+ * field in bit order, as dtype.  phi, u, p, T follow Eqs. Moment_Phi,
+ * Velocity, Pressure and Moment_Temp. */
+lbm_status lbm_get_fields(lbm_ctx* ctx, uint32_t mask, void* dev_out, int32_t dtype);
+
+/* FP64 diagnostics at the current populations (host out[5]): sum(phi),
+ * enthalpy sum(T) + (L/Cp)(sum(phi) + sum(phi_prev))/2, vapour fraction
+ * sum(phi)/N, max|u|, and the count of non-finite nodes.  Deterministic
+ * (fixed reduction tree).  Synchronises the stream; returns
+ * LBM_E_UNSTABLE if the count is non-zero. */
+lbm_status lbm_diagnostics(lbm_ctx* ctx, double out[5]);
+
+/* Checkpoint / resume: the raw state (populations, lagged phi and q) as an
+ * opaque byte blob of lbm_state_size bytes, copied device-to-device. */
+lbm_status lbm_state_size(const lbm_ctx* ctx, size_t* bytes);
+lbm_status lbm_get_state(lbm_ctx* ctx, void* dev_out, size_t bytes);
+lbm_status lbm_set_state(lbm_ctx* ctx, const void* dev_in, size_t bytes);
+
+/* Steps taken since lbm_init_fields / lbm_set_state (host out). */
+lbm_status lbm_get_step(const lbm_ctx* ctx, int64_t* out);
+
+/* Wait for all work queued on the context's stream; reports HIP errors. */
+lbm_status lbm_sync(lbm_ctx* ctx);
+
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Message of the last error on the calling thread (never NULL). */
+const char* lbm_last_error(void);
+
+/* Library version string. */
+const char* lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

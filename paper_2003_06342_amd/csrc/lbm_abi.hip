@@ -1,0 +1,478 @@
+// C ABI of the phase-change LBM library (see include/lbm.h).
+//
+// Host side: parameter validation, workspace carving, relaxation rates and
+// codec constants, kernel launches on the caller's stream, and the
+// deterministic FP64 diagnostics reduction.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "../../include/lbm.h"
+#include "lbm_kernels.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+lbm_status fail(lbm_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+lbm_status fail(lbm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+lbm_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return LBM_OK;
+  return fail(LBM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Layout {
+  int Qf, Qg, Qs, Qtot;
+  int px;
+  long long slab;
+  size_t elem, sc_elem, real_elem;
+  size_t pops, scal, faces[3][2], partials;
+  size_t total;
+  int nblocks;
+};
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params prm;
+  Layout L;
+  int ns, heat;
+  char* ws;
+  void* pops[2];
+  void* phip[2];
+  void* qp[2];
+  void* tw[3][2];
+  double* partials;
+  double* red;
+  int cur;
+  int64_t step;
+  int initialized;
+  hipStream_t stream;
+  double ref[3], scale[3];
+};
+
+namespace {
+
+int q_of(int lat) { return lat; }
+
+lbm_status validate(const lbm_params* p) {
+  if (!p) return fail(LBM_E_INVAL, "params is NULL");
+  if (p->dim != 2 && p->dim != 3) return fail(LBM_E_INVAL, "dim must be 2 or 3");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_E_INVAL, "grid sizes must be >= 1");
+  if (p->dim == 2) {
+    if (p->nz != 1) return fail(LBM_E_INVAL, "2-D needs nz == 1");
+    if (p->lat_f != LBM_D2Q9 || p->lat_g != LBM_D2Q9 || p->lat_s != LBM_D2Q9)
+      return fail(LBM_E_UNSUPPORTED, "2-D supports D2Q9 for f, g and s");
+  } else {
+    if (p->lat_f != LBM_D3Q19 || p->lat_g != LBM_D3Q7 || p->lat_s != LBM_D3Q7)
+      return fail(LBM_E_UNSUPPORTED, "3-D supports D3Q19 (f) with D3Q7 (g, s)");
+    if (p->bc[0] != LBM_BC_PERIODIC || p->bc[1] != LBM_BC_PERIODIC)
+      return fail(LBM_E_UNSUPPORTED, "3-D supports walls on z only");
+  }
+  for (int a = 0; a < 3; ++a)
+    if (p->bc[a] != LBM_BC_PERIODIC && p->bc[a] != LBM_BC_WALL)
+      return fail(LBM_E_INVAL, "bc[%d] must be LBM_BC_PERIODIC or LBM_BC_WALL", a);
+  if (p->storage < LBM_ST_F64 || p->storage > LBM_ST_BF16_DEV)
+    return fail(LBM_E_INVAL, "unknown storage %d", p->storage);
+  const double pos[] = {p->nu_l, p->nu_g, p->mobility, p->alpha_l, p->alpha_g, p->W, p->rho_l, p->rho_g};
+  const char* nm[] = {"nu_l", "nu_g", "mobility", "alpha_l", "alpha_g", "W", "rho_l", "rho_g"};
+  for (int i = 0; i < 8; ++i)
+    if (!(pos[i] > 0) || !std::isfinite(pos[i]))
+      return fail(LBM_E_INVAL, "%s must be finite and > 0 (tau > 0, omega < 2)", nm[i]);
+  if ((p->flags & LBM_HEAT) && !(p->L_over_cp > 0)) return fail(LBM_E_INVAL, "L_over_cp must be > 0");
+  if ((p->flags & LBM_PHASE_CHANGE) && !(p->flags & LBM_HEAT))
+    return fail(LBM_E_INVAL, "LBM_PHASE_CHANGE needs LBM_HEAT");
+  if (p->A_coef < 0) return fail(LBM_E_INVAL, "A_coef must be >= 0");
+  if (!(p->sigma >= 0)) return fail(LBM_E_INVAL, "sigma must be >= 0");
+  if ((long long)p->nx * p->ny * p->nz > (1LL << 31)) return fail(LBM_E_INVAL, "grid too large");
+  return LBM_OK;
+}
+
+Layout layout(const lbm_params* p) {
+  Layout L{};
+  const bool ns = p->flags & LBM_NS, heat = p->flags & LBM_HEAT;
+  L.Qf = ns ? q_of(p->lat_f) : 0;
+  L.Qg = q_of(p->lat_g);
+  L.Qs = heat ? q_of(p->lat_s) : 0;
+  L.Qtot = L.Qf + L.Qg + L.Qs;
+  L.px = (p->nx + 63) / 64 * 64;
+  L.slab = (long long)L.px * p->ny * p->nz;
+  L.elem = p->storage == LBM_ST_F64 ? 8 : (p->storage == LBM_ST_F32 ? 4 : 2);
+  L.sc_elem = p->storage == LBM_ST_F64 ? 8 : 4;
+  L.real_elem = p->storage == LBM_ST_F64 ? 8 : 4;
+  L.pops = align256((size_t)L.Qtot * L.slab * L.elem);
+  L.scal = align256((size_t)L.slab * L.sc_elem);
+  size_t tot = 2 * L.pops + 4 * L.scal;
+  const int n[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 2; ++s) {
+      L.faces[a][s] = 0;
+      if (p->bc[a] == LBM_BC_WALL) {
+        const size_t face = (size_t)n[0] * n[1] * n[2] / n[a];
+        L.faces[a][s] = align256(face * L.real_elem);
+        tot += L.faces[a][s];
+      }
+    }
+  L.nblocks = p->dim == 2 ? step2d_blocks(p->nx, p->ny) : 1;
+  L.partials = align256((size_t)(L.nblocks * NPART + 8) * sizeof(double));
+  tot += L.partials;
+  L.total = tot;
+  return L;
+}
+
+template <class Real, class Store>
+KArgs<Real, Store> make_args(const lbm_ctx* c) {
+  const lbm_params& p = c->prm;
+  KArgs<Real, Store> a{};
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.nz = p.nz;
+  a.px = c->L.px;
+  a.slab = c->L.slab;
+  for (int d = 0; d < 3; ++d) a.wall[d] = p.bc[d] == LBM_BC_WALL;
+  a.off_f = 0;
+  a.off_g = c->L.Qf;
+  a.off_s = c->L.Qf + c->L.Qg;
+  for (int d = 0; d < 3; ++d)
+    for (int s = 0; s < 2; ++s) {
+      a.Tw[d][s] = (const Real*)c->tw[d][s];
+      a.phi_w[d][s] = (Real)p.phi_wall[d][s];
+    }
+  for (int k = 0; k < 3; ++k) {
+    a.ref[k] = (Real)c->ref[k];
+    a.scale[k] = (Real)c->scale[k];
+    a.inv_scale[k] = (Real)(1.0 / c->scale[k]);
+  }
+  const double cs2g = p.dim == 2 ? 1.0 / 3.0 : 0.25;
+  a.rho_l = (Real)p.rho_l;
+  a.rho_g = (Real)p.rho_g;
+  a.K = (Real)(1.5 * p.W * p.sigma);          // Eq. Def_K-H
+  a.H = (Real)(12.0 * p.sigma / p.W);
+  a.four_over_W = (Real)(4.0 / p.W);
+  const double eps = p.eps_n > 0 ? p.eps_n : 1e-9;
+  a.eps2 = (Real)(eps * eps);
+  for (int d = 0; d < 3; ++d) {
+    a.grav[d] = (Real)p.gravity[d];
+    a.body[d] = (Real)p.body_force[d];
+  }
+  a.nu_l = (Real)p.nu_l;
+  a.nu_g = (Real)p.nu_g;
+  a.alpha_l = (Real)p.alpha_l;
+  a.alpha_g = (Real)p.alpha_g;
+  a.Lcp = (Real)p.L_over_cp;
+  a.inv_Lcp = (Real)(p.L_over_cp > 0 ? 1.0 / p.L_over_cp : 0.0);
+  a.T_sat = (Real)p.T_sat;
+  a.theta_I = (Real)p.theta_I;
+  const double A = p.A_coef > 0 ? p.A_coef : 10.0 / 48.0;
+  a.qcoef = (Real)(4.0 / (A * p.W * p.W));
+  a.omega_g = (Real)(1.0 / (p.mobility / cs2g + 0.5));   // M = tau_g c_s^2
+  a.M_over_cs2g = (Real)(p.mobility / cs2g);
+  a.prod_fac = (Real)(p.rho_g * (1.0 / p.rho_g - 1.0 / p.rho_l));
+  a.visc_linear = (p.flags & LBM_VISC_LINEAR) ? 1 : 0;
+  a.geq_cac = (p.flags & LBM_GEQ_CAC) ? 1 : 0;
+  a.phase_change = (p.flags & LBM_PHASE_CHANGE) ? 1 : 0;
+  const int cur = c->cur;
+  a.A = (const Store*)c->pops[cur];
+  a.B = (Store*)c->pops[1 - cur];
+  a.A_phip = (const typename KArgs<Real, Store>::Sc*)c->phip[cur];
+  a.A_qp = (const typename KArgs<Real, Store>::Sc*)c->qp[cur];
+  a.B_phip = (typename KArgs<Real, Store>::Sc*)c->phip[1 - cur];
+  a.B_qp = (typename KArgs<Real, Store>::Sc*)c->qp[1 - cur];
+  return a;
+}
+
+// Dispatch a callable on the (Real, Store) pair of the context.
+template <class Fn>
+hipError_t dispatch(const lbm_ctx* c, Fn&& fn) {
+  switch (c->prm.storage) {
+    case LBM_ST_F64: return fn(make_args<double, double>(c));
+    case LBM_ST_F32: return fn(make_args<float, float>(c));
+    case LBM_ST_F16_DEV: return fn(make_args<float, __half>(c));
+    default: return fn(make_args<float, __hip_bfloat16>(c));
+  }
+}
+
+__global__ void k_fill(void* dst, long long n, double v, int f64) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (f64) ((double*)dst)[i] = v;
+  else ((float*)dst)[i] = (float)v;
+}
+__global__ void k_convert(void* dst, int dst_f64, const void* src, int src_f64, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = src_f64 ? ((const double*)src)[i] : (double)((const float*)src)[i];
+  if (dst_f64) ((double*)dst)[i] = v;
+  else ((float*)dst)[i] = (float)v;
+}
+
+__global__ void k_reduce(const double* partials, int nb, double* out) {
+  __shared__ double red[NPART][4];
+  double s[NPART] = {0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    s[0] += partials[(long long)b * NPART + 0];
+    s[1] += partials[(long long)b * NPART + 1];
+    s[2] += partials[(long long)b * NPART + 2];
+    s[3] = fmax(s[3], partials[(long long)b * NPART + 3]);
+    s[4] += partials[(long long)b * NPART + 4];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k = 0; k < NPART; ++k) s[k] = (k == 3) ? wave_max_d(s[k]) : wave_sum_d(s[k]);
+  if (lane == 0)
+    for (int k = 0; k < NPART; ++k) red[k][wv] = s[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NPART; ++k) {
+      double v = red[k][0];
+      for (int w = 1; w < 4; ++w) v = (k == 3) ? fmax(v, red[k][w]) : v + red[k][w];
+      out[k] = v;
+    }
+  }
+}
+
+}  // namespace
+
+namespace lbm {
+hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partials, nblocks, out);
+  return hipGetLastError();
+}
+}  // namespace lbm
+
+extern "C" {
+
+lbm_status lbm_workspace_size(const lbm_params* prm, size_t* bytes) {
+  if (!bytes) return fail(LBM_E_INVAL, "bytes is NULL");
+  lbm_status s = validate(prm);
+  if (s != LBM_OK) return s;
+  if (prm->dim == 3) return fail(LBM_E_UNSUPPORTED, "3-D step not built");
+  *bytes = layout(prm).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_params* prm, void* ws, size_t bytes, void* stream, lbm_ctx** out) {
+  if (!out) return fail(LBM_E_INVAL, "out is NULL");
+  *out = nullptr;
+  lbm_status s = validate(prm);
+  if (s != LBM_OK) return s;
+  if (prm->dim == 3) return fail(LBM_E_UNSUPPORTED, "3-D step not built");
+  const Layout L = layout(prm);
+  if (!ws) return fail(LBM_E_INVAL, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(LBM_E_INVAL, "workspace must be 256-byte aligned");
+  if (bytes < L.total)
+    return fail(LBM_E_NOMEM, "workspace has %zu bytes, needs %zu", bytes, L.total);
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return fail(LBM_E_NOMEM, "host allocation failed");
+  c->prm = *prm;
+  c->L = L;
+  c->ns = (prm->flags & LBM_NS) != 0;
+  c->heat = (prm->flags & LBM_HEAT) != 0;
+  c->stream = (hipStream_t)stream;
+  c->ws = (char*)ws;
+  char* p = c->ws;
+  c->pops[0] = p;  p += L.pops;
+  c->pops[1] = p;  p += L.pops;
+  c->phip[0] = p;  p += L.scal;
+  c->qp[0] = p;    p += L.scal;
+  c->phip[1] = p;  p += L.scal;
+  c->qp[1] = p;    p += L.scal;
+  for (int a = 0; a < 3; ++a)
+    for (int sd = 0; sd < 2; ++sd) {
+      c->tw[a][sd] = L.faces[a][sd] ? (void*)p : nullptr;
+      p += L.faces[a][sd];
+    }
+  c->partials = (double*)p;
+  c->red = c->partials + (size_t)L.nblocks * NPART;
+  // 16-bit deviation codec: phi about 1/2, T about the mean wall value,
+  // f (gauge pressure) about 0; scale 2^12 keeps |dev| in FP16's normal range.
+  double tref = prm->T_sat, cnt = 1;
+  for (int a = 0; a < 3; ++a)
+    if (prm->bc[a] == LBM_BC_WALL) {
+      tref += prm->T_wall[a][0] + prm->T_wall[a][1];
+      cnt += 2;
+    }
+  const bool f16 = prm->storage == LBM_ST_F16_DEV, b16 = prm->storage == LBM_ST_BF16_DEV;
+  c->ref[0] = 0.0;
+  c->ref[1] = (f16 || b16) ? 0.5 : 0.0;
+  c->ref[2] = (f16 || b16) ? tref / cnt : 0.0;
+  for (int k = 0; k < 3; ++k) c->scale[k] = f16 ? 4096.0 : 1.0;
+  c->cur = 0;
+  // wall rows start at the scalar face values
+  const int n[3] = {prm->nx, prm->ny, prm->nz};
+  for (int a = 0; a < 3; ++a)
+    for (int sd = 0; sd < 2; ++sd)
+      if (c->tw[a][sd]) {
+        const long long face = (long long)n[0] * n[1] * n[2] / n[a];
+        hipLaunchKernelGGL(k_fill, dim3((face + 255) / 256), dim3(256), 0, c->stream, c->tw[a][sd],
+                           face, prm->T_wall[a][sd], prm->storage == LBM_ST_F64 ? 1 : 0);
+      }
+  s = hip_check(hipGetLastError(), "lbm_create");
+  if (s != LBM_OK) {
+    delete c;
+    return s;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_ctx* c, const void* phi0, const void* T0, const void* u0,
+                           const void* p0, int32_t dtype) {
+  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  if (!phi0) return fail(LBM_E_INVAL, "phi0 is NULL");
+  if (c->heat && !T0) return fail(LBM_E_INVAL, "T0 is NULL but LBM_HEAT is set");
+  if (dtype != LBM_DT_F32 && dtype != LBM_DT_F64) return fail(LBM_E_INVAL, "bad dtype");
+  // the init kernel writes the current buffer: pretend it is B of a step
+  c->cur = 1;
+  const int f64 = dtype == LBM_DT_F64;
+  hipError_t e = dispatch(c, [&](auto a) {
+    return launch_init2d(a, c->ns, c->heat, phi0, T0, u0, p0, f64, c->stream);
+  });
+  c->cur = 0;
+  c->step = 0;
+  c->initialized = 1;
+  return hip_check(e, "lbm_init_fields");
+}
+
+lbm_status lbm_set_wall_T(lbm_ctx* c, int32_t axis, int32_t side, const void* face, int32_t dtype) {
+  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  if (axis < 0 || axis > 2 || side < 0 || side > 1) return fail(LBM_E_INVAL, "bad face");
+  if (!c->tw[axis][side]) return fail(LBM_E_INVAL, "axis %d is not walled", axis);
+  if (!face) return fail(LBM_E_INVAL, "face is NULL");
+  if (dtype != LBM_DT_F32 && dtype != LBM_DT_F64) return fail(LBM_E_INVAL, "bad dtype");
+  const int n[3] = {c->prm.nx, c->prm.ny, c->prm.nz};
+  const long long cnt = (long long)n[0] * n[1] * n[2] / n[axis];
+  hipLaunchKernelGGL(k_convert, dim3((cnt + 255) / 256), dim3(256), 0, c->stream, c->tw[axis][side],
+                     c->prm.storage == LBM_ST_F64 ? 1 : 0, face, dtype == LBM_DT_F64 ? 1 : 0, cnt);
+  return hip_check(hipGetLastError(), "lbm_set_wall_T");
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
+  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  if (!c->initialized) return fail(LBM_E_STATE, "lbm_step before lbm_init_fields / lbm_set_state");
+  if (nsteps < 0) return fail(LBM_E_INVAL, "nsteps < 0");
+  for (int64_t k = 0; k < nsteps; ++k) {
+    hipError_t e = dispatch(c, [&](auto a) {
+      return launch_step2d(a, c->ns, c->heat, MODE_STEP, c->stream);
+    });
+    if (e != hipSuccess) return hip_check(e, "lbm_step");
+    c->cur = 1 - c->cur;
+    ++c->step;
+  }
+  return LBM_OK;
+}
+
+static lbm_status run_macro(lbm_ctx* c, uint32_t mask, void* out, int f64, double* partials) {
+  hipError_t e = dispatch(c, [&](auto a) {
+    a.out = out;
+    a.out_f64 = f64;
+    a.out_mask = mask;
+    a.partials = partials;
+    return launch_step2d(a, c->ns, c->heat, MODE_MACRO, c->stream);
+  });
+  return hip_check(e, "macro pass");
+}
+
+lbm_status lbm_get_fields(lbm_ctx* c, uint32_t mask, void* out, int32_t dtype) {
+  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  if (!c->initialized) return fail(LBM_E_STATE, "lbm_get_fields before initialisation");
+  if (mask & ~63u) return fail(LBM_E_INVAL, "unknown field bits");
+  if (mask && !out) return fail(LBM_E_INVAL, "out is NULL");
+  if (dtype != LBM_DT_F32 && dtype != LBM_DT_F64) return fail(LBM_E_INVAL, "bad dtype");
+  if (!mask) return LBM_OK;
+  return run_macro(c, mask, out, dtype == LBM_DT_F64, nullptr);
+}
+
+lbm_status lbm_diagnostics(lbm_ctx* c, double out[5]) {
+  if (!c || !out) return fail(LBM_E_INVAL, "NULL argument");
+  if (!c->initialized) return fail(LBM_E_STATE, "lbm_diagnostics before initialisation");
+  lbm_status s = run_macro(c, 0u, nullptr, 0, c->partials);
+  if (s != LBM_OK) return s;
+  s = hip_check(launch_reduce(c->partials, c->L.nblocks, c->red, c->stream), "reduce");
+  if (s != LBM_OK) return s;
+  double r[NPART];
+  s = hip_check(hipMemcpyAsync(r, c->red, sizeof r, hipMemcpyDeviceToHost, c->stream), "copy");
+  if (s != LBM_OK) return s;
+  s = hip_check(hipStreamSynchronize(c->stream), "lbm_diagnostics");
+  if (s != LBM_OK) return s;
+  const double N = (double)c->prm.nx * c->prm.ny * c->prm.nz;
+  const double Lcp = c->heat ? c->prm.L_over_cp : 0.0;
+  out[0] = r[0];
+  out[1] = r[1] + Lcp * 0.5 * (r[0] + r[2]);
+  out[2] = r[0] / N;
+  out[3] = r[3];
+  out[4] = r[4];
+  if (r[4] != 0) return fail(LBM_E_UNSTABLE, "%.0f non-finite nodes", r[4]);
+  return LBM_OK;
+}
+
+lbm_status lbm_state_size(const lbm_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(LBM_E_INVAL, "NULL argument");
+  *bytes = c->L.pops + 2 * c->L.scal;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_ctx* c, void* out, size_t bytes) {
+  if (!c || !out) return fail(LBM_E_INVAL, "NULL argument");
+  if (!c->initialized) return fail(LBM_E_STATE, "no state yet");
+  if (bytes < c->L.pops + 2 * c->L.scal) return fail(LBM_E_NOMEM, "state buffer too small");
+  char* o = (char*)out;
+  hipError_t e = hipMemcpyAsync(o, c->pops[c->cur], c->L.pops, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(o + c->L.pops, c->phip[c->cur], c->L.scal, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(o + c->L.pops + c->L.scal, c->qp[c->cur], c->L.scal, hipMemcpyDeviceToDevice,
+                       c->stream);
+  return hip_check(e, "lbm_get_state");
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const void* in, size_t bytes) {
+  if (!c || !in) return fail(LBM_E_INVAL, "NULL argument");
+  if (bytes < c->L.pops + 2 * c->L.scal) return fail(LBM_E_NOMEM, "state buffer too small");
+  const char* i = (const char*)in;
+  hipError_t e = hipMemcpyAsync(c->pops[c->cur], i, c->L.pops, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->phip[c->cur], i + c->L.pops, c->L.scal, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->qp[c->cur], i + c->L.pops + c->L.scal, c->L.scal, hipMemcpyDeviceToDevice,
+                       c->stream);
+  c->initialized = 1;
+  c->step = 0;
+  return hip_check(e, "lbm_set_state");
+}
+
+lbm_status lbm_get_step(const lbm_ctx* c, int64_t* out) {
+  if (!c || !out) return fail(LBM_E_INVAL, "NULL argument");
+  *out = c->step;
+  return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_ctx* c) {
+  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  return hip_check(hipStreamSynchronize(c->stream), "lbm_sync");
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+const char* lbm_version(void) { return "lbm-phasechange-gfx950 0.1"; }
+
+}  // extern "C"

@@ -1,0 +1,561 @@
+// 2-D fused time step (D2Q9 for f, g and s; D2Q9 stencils) for gfx950.
+//
+// One workgroup (256 lanes, 4 wave64) owns a 64 x 16 tile and runs three
+// LDS phases per step:
+//   1. phi = sum g_bar + q_prev/2 (Eq. Moment_Phi, lagged production) on the
+//      tile plus a 2-node halo, pulled straight from buffer A with the wall
+//      links applied; stored in LDS.  Wall ghosts 2 phi_w - phi_b.
+//   2. u (Eq. Velocity) on the tile plus a 1-node halo: directional-derivative
+//      gradient and Laplacian of phi from LDS (Eqs. Grad, Laplacian),
+//      chemical potential, forces and the first moment of the pulled f.
+//      Stored in LDS.  No-slip ghosts -u_b.
+//   3. every tile node: pull f, g, s, moments (Eqs. Pressure, Moment_Temp),
+//      d_t phi, div(u phi) from LDS, production (Eq. ProductionRate),
+//      equilibria, sources, BGK collision; write to buffer B (pull scheme:
+//      the next step's gather does the streaming).
+// The halo recomputation keeps every step a single pass over HBM: each
+// population is read once from A and written once to B (halo re-reads hit
+// L2), plus phi_prev and q_prev.
+#include "lbm_device.h"
+#include "lbm_kernels.h"
+
+namespace lbm {
+
+constexpr int TX2 = 64, TY2 = 16, NT2 = 256;
+constexpr int R1X = TX2 + 4, R1Y = TY2 + 4;   // phi region (halo 2)
+constexpr int R2X = TX2 + 2, R2Y = TY2 + 2;   // u region (halo 1)
+
+// Pull the Q populations of family FAM (0 f, 1 g, 2 s) arriving at node
+// (x, y).  A link whose source lies beyond a wall reflects at the node:
+// bounce-back for f, anti-bounce-back -v_{i'} + 2 w_i V_w for g and s
+// (Sec. 3.3).  The y wall takes precedence over the x wall at corners.
+template <class Lat, int FAM, class Real, class Store>
+__device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real* v) {
+  using C = Codec<Real, Store>;
+  const int off = FAM == 0 ? a.off_f : (FAM == 1 ? a.off_g : a.off_s);
+  const Real ref = a.ref[FAM], inv = a.inv_scale[FAM];
+  const long long node = (long long)y * a.px + x;
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) {
+    const int cx = Lat::cx(i), cy = Lat::cy(i);
+    int sx = x - cx, sy = y - cy;
+    const bool oy = (cy != 0) && a.wall[1] && (sy < 0 || sy >= a.ny);
+    const bool ox = (cx != 0) && !oy && a.wall[0] && (sx < 0 || sx >= a.nx);
+    const Real wref = (Real)Lat::w(i) * ref;
+    if (oy || ox) {
+      const int j = Lat::opp(i);
+      Real r = C::dec(a.A[(long long)(off + j) * a.slab + node], wref, inv);
+      if (FAM != 0) {
+        Real V;
+        if (oy) {
+          const int side = sy < 0 ? 0 : 1;
+          V = FAM == 1 ? a.phi_w[1][side] : a.Tw[1][side][x];
+        } else {
+          const int side = sx < 0 ? 0 : 1;
+          V = FAM == 1 ? a.phi_w[0][side] : a.Tw[0][side][y];
+        }
+        r = -r + (Real)2 * (Real)Lat::w(i) * V;
+      }
+      v[i] = r;
+    } else {
+      if (cx != 0 && !a.wall[0]) sx = wrap1(sx, a.nx);
+      if (cy != 0 && !a.wall[1]) sy = wrap1(sy, a.ny);
+      v[i] = C::dec(a.A[(long long)(off + i) * a.slab + (long long)sy * a.px + sx], wref, inv);
+    }
+  }
+}
+
+// Directional-derivative gradient and Laplacian (Eqs. DerivDirec_Grad, Grad,
+// DerivDirect_Laplacian, Laplacian) of an LDS field at (ry, rx).
+template <class Real, int RX>
+__device__ inline void stencil2d(const Real (*s)[RX], int ry, int rx, Real* g, Real& lap) {
+  const Real c = s[ry][rx];
+  Real gx = 0, gy = 0, l = 0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+    const Real w = (Real)D2Q9::w(i);
+    const Real p = s[ry + cy][rx + cx], m = s[ry - cy][rx - cx];
+    const Real dd = (Real)0.5 * (p - m);
+    gx += w * (Real)cx * dd;
+    gy += w * (Real)cy * dd;
+    l += w * (p - (Real)2 * c + m);
+  }
+  g[0] = gx * (Real)3;
+  g[1] = gy * (Real)3;
+  g[2] = 0;
+  lap = l * (Real)3;
+}
+
+// div(u phi): the Eq. Grad stencil applied to u_a phi, a-th component, summed.
+template <class Real>
+__device__ inline Real divergence2d(const Real (*sphi)[R1X], const Real (*sux)[R2X],
+                                    const Real (*suy)[R2X], int ry2, int rx2) {
+  Real d = 0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+    const Real w = (Real)D2Q9::w(i);
+    const Real pp = sphi[ry2 + 1 + cy][rx2 + 1 + cx], pm = sphi[ry2 + 1 - cy][rx2 + 1 - cx];
+    if (cx != 0)
+      d += w * (Real)cx * (Real)0.5 * (sux[ry2 + cy][rx2 + cx] * pp - sux[ry2 - cy][rx2 - cx] * pm);
+    if (cy != 0)
+      d += w * (Real)cy * (Real)0.5 * (suy[ry2 + cy][rx2 + cx] * pp - suy[ry2 - cy][rx2 - cx] * pm);
+  }
+  return d * (Real)3;
+}
+
+// Map a region coordinate to the domain: wraps periodic axes; returns false
+// for points beyond a wall (ghosts).
+__device__ inline bool to_domain(int& g, int n, int wall) {
+  if (wall) return g >= 0 && g < n;
+  g = wrapmod(g, n);
+  return true;
+}
+
+// Mirror of a ghost coordinate across the half-way wall (-1 <-> 0, n <-> n-1).
+__device__ inline int mirror(int g, int n) { return g < 0 ? -1 - g : 2 * n - 1 - g; }
+
+template <class Store, class Real, bool NS, bool HEAT, int MODE>
+__global__ __launch_bounds__(NT2) void k_step2d(const KArgs<Real, Store> a) {
+  using C = Codec<Real, Store>;
+  using Sc = typename ScalarOf<Store>::T;
+  __shared__ Real sphi[R1Y][R1X];
+  __shared__ Real sux[R2Y][R2X];
+  __shared__ Real suy[R2Y][R2X];
+
+  const int tiles_x = (a.nx + TX2 - 1) / TX2;
+  const int ntiles = tiles_x * ((a.ny + TY2 - 1) / TY2);
+  // XCD-aware order: hardware deals blocks to the 8 XCDs round-robin; give
+  // each XCD a contiguous band of tiles so neighbouring tiles share an L2.
+  int t = blockIdx.x;
+  const int full = (ntiles / 8) * 8;
+  if (t < full) t = (t % 8) * (full / 8) + t / 8;
+  const int x0 = (t % tiles_x) * TX2, y0 = (t / tiles_x) * TY2;
+  const int tid = threadIdx.x;
+
+  // ---- phase 1: phi on the tile + 2-halo --------------------------------
+  for (int k = tid; k < R1X * R1Y; k += NT2) {
+    const int ry = k / R1X, rx = k - ry * R1X;
+    int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
+    Real v = 0;
+    if (to_domain(gx, a.nx, a.wall[0]) && to_domain(gy, a.ny, a.wall[1])) {
+      Real g[9];
+      gather2d<D2Q9, 1>(a, gx, gy, g);
+      Real s = 0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) s += g[i];
+      v = s + (Real)0.5 * (Real)a.A_qp[(long long)gy * a.px + gx];
+    }
+    sphi[ry][rx] = v;
+  }
+  __syncthreads();
+  if (a.wall[0]) {   // x ghosts first, then y ghosts (corners compose)
+    for (int k = tid; k < R1X * R1Y; k += NT2) {
+      const int ry = k / R1X, rx = k - ry * R1X;
+      const int gx = x0 - 2 + rx;
+      if (gx < 0 || gx >= a.nx) {
+        const int mx = mirror(gx, a.nx) - (x0 - 2);
+        if (mx >= 0 && mx < R1X) sphi[ry][rx] = (Real)2 * a.phi_w[0][gx < 0 ? 0 : 1] - sphi[ry][mx];
+      }
+    }
+    __syncthreads();
+  }
+  if (a.wall[1]) {
+    for (int k = tid; k < R1X * R1Y; k += NT2) {
+      const int ry = k / R1X, rx = k - ry * R1X;
+      const int gy = y0 - 2 + ry;
+      if (gy < 0 || gy >= a.ny) {
+        const int my = mirror(gy, a.ny) - (y0 - 2);
+        if (my >= 0 && my < R1Y) sphi[ry][rx] = (Real)2 * a.phi_w[1][gy < 0 ? 0 : 1] - sphi[my][rx];
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- phase 2: u on the tile + 1-halo -----------------------------------
+  if constexpr (NS && HEAT) {
+    for (int k = tid; k < R2X * R2Y; k += NT2) {
+      const int ry = k / R2X, rx = k - ry * R2X;
+      int gx = x0 - 1 + rx, gy = y0 - 1 + ry;
+      Real ux = 0, uy = 0;
+      if (to_domain(gx, a.nx, a.wall[0]) && to_domain(gy, a.ny, a.wall[1])) {
+        Real gphi[3], lphi, rho, mu, F[3];
+        stencil2d<Real, R1X>(sphi, ry + 1, rx + 1, gphi, lphi);
+        forces(a, sphi[ry + 1][rx + 1], gphi, lphi, rho, mu, F);
+        Real f[9];
+        gather2d<D2Q9, 0>(a, gx, gy, f);
+        Real mx = 0, my = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          mx += (Real)D2Q9::cx(i) * f[i];
+          my += (Real)D2Q9::cy(i) * f[i];
+        }
+        const Real ir = (Real)1 / rho;
+        ux = ((Real)3 * mx + (Real)0.5 * F[0]) * ir;
+        uy = ((Real)3 * my + (Real)0.5 * F[1]) * ir;
+      }
+      sux[ry][rx] = ux;
+      suy[ry][rx] = uy;
+    }
+    __syncthreads();
+    if (a.wall[0]) {
+      for (int k = tid; k < R2X * R2Y; k += NT2) {
+        const int ry = k / R2X, rx = k - ry * R2X;
+        const int gx = x0 - 1 + rx;
+        if (gx < 0 || gx >= a.nx) {
+          const int mx = mirror(gx, a.nx) - (x0 - 1);
+          if (mx >= 0 && mx < R2X) {
+            sux[ry][rx] = -sux[ry][mx];
+            suy[ry][rx] = -suy[ry][mx];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (a.wall[1]) {
+      for (int k = tid; k < R2X * R2Y; k += NT2) {
+        const int ry = k / R2X, rx = k - ry * R2X;
+        const int gy = y0 - 1 + ry;
+        if (gy < 0 || gy >= a.ny) {
+          const int my = mirror(gy, a.ny) - (y0 - 1);
+          if (my >= 0 && my < R2Y) {
+            sux[ry][rx] = -sux[my][rx];
+            suy[ry][rx] = -suy[my][rx];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- phase 3: the tile's nodes ------------------------------------------
+  double acc_phi = 0, acc_T = 0, acc_phip = 0, acc_umax = 0, acc_bad = 0;
+  const int lx = tid % TX2;
+  for (int r = tid / TX2; r < TY2; r += NT2 / TX2) {
+    const int x = x0 + lx, y = y0 + r;
+    if (x >= a.nx || y >= a.ny) continue;
+    const long long node = (long long)y * a.px + x;
+    NodeMacro<Real> m;
+    m.phi = sphi[r + 2][lx + 2];
+    stencil2d<Real, R1X>(sphi, r + 2, lx + 2, m.gphi, m.lphi);
+    forces(a, m.phi, m.gphi, m.lphi, m.rho, m.mu, m.F);
+    const Real drho = a.rho_g - a.rho_l;
+    const Real inrm = rsqrt_t<Real>(m.gphi[0] * m.gphi[0] + m.gphi[1] * m.gphi[1] + a.eps2);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      m.grho[d] = drho * m.gphi[d];
+      m.n[d] = m.gphi[d] * inrm;
+    }
+    Real f[9], g[9], s[9];
+    Real m0f = 0;
+    m.u[0] = m.u[1] = m.u[2] = 0;
+    if constexpr (NS) {
+      gather2d<D2Q9, 0>(a, x, y, f);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) m0f += f[i];
+      if constexpr (HEAT) {
+        m.u[0] = sux[r + 1][lx + 1];
+        m.u[1] = suy[r + 1][lx + 1];
+      } else {
+        Real mx = 0, my = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          mx += (Real)D2Q9::cx(i) * f[i];
+          my += (Real)D2Q9::cy(i) * f[i];
+        }
+        const Real ir = (Real)1 / m.rho;
+        m.u[0] = ((Real)3 * mx + (Real)0.5 * m.F[0]) * ir;
+        m.u[1] = ((Real)3 * my + (Real)0.5 * m.F[1]) * ir;
+      }
+    }
+    gather2d<D2Q9, 1>(a, x, y, g);
+    const Real phip = (Real)a.A_phip[node];
+    m.dtphi = m.phi - phip;
+    m.alpha = diffusivity(a, m.phi);
+    m.D = 0;
+    m.T = 0;
+    m.q = 0;
+    if constexpr (HEAT) {
+      gather2d<D2Q9, 2>(a, x, y, s);
+      if constexpr (NS) m.D = divergence2d<Real>(sphi, sux, suy, r + 1, lx + 1);
+      Real m0s = 0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) m0s += s[i];
+      m.T = m0s - (Real)0.5 * a.Lcp * (m.dtphi + m.D);
+      m.q = production(a, m.phi, m.T, m.alpha);
+    }
+    const Real cs2 = (Real)(1.0 / 3.0);
+    m.p = 0;
+    if constexpr (NS) {
+      const Real udr = m.u[0] * m.grho[0] + m.u[1] * m.grho[1];
+      m.p = m0f + (Real)0.5 * (cs2 * udr + m.rho * cs2 * m.q * a.prod_fac);
+    }
+    if constexpr (MODE == MODE_STEP) {
+      if constexpr (NS) {
+        m.nu = viscosity(a, m.phi);
+        const Real om = (Real)1 / (m.nu * (Real)3 + (Real)0.5);
+        collide_f<D2Q9>(f, m, m.rho * cs2 * m.q * a.prod_fac, om);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+          a.B[(long long)(a.off_f + i) * a.slab + node] =
+              C::enc(f[i], (Real)D2Q9::w(i) * a.ref[0], a.scale[0]);
+      }
+      collide_g<D2Q9>(a, g, m);
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+        a.B[(long long)(a.off_g + i) * a.slab + node] =
+            C::enc(g[i], (Real)D2Q9::w(i) * a.ref[1], a.scale[1]);
+      if constexpr (HEAT) {
+        const Real om = (Real)1 / (m.alpha * (Real)3 + (Real)0.5);
+        collide_s<D2Q9>(a, s, m, om);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+          a.B[(long long)(a.off_s + i) * a.slab + node] =
+              C::enc(s[i], (Real)D2Q9::w(i) * a.ref[2], a.scale[2]);
+      }
+      a.B_phip[node] = (Sc)m.phi;
+      a.B_qp[node] = (Sc)m.q;
+    } else {
+      const long long plane = (long long)a.nx * a.ny * a.nz;
+      const long long idx = (long long)y * a.nx + x;
+      const Real vals[6] = {m.phi, m.p, m.u[0], m.u[1], (Real)0, m.T};
+      int k = 0;
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        if (a.out_mask & (1u << b)) {
+          if (a.out_f64)
+            ((double*)a.out)[k * plane + idx] = (double)vals[b];
+          else
+            ((float*)a.out)[k * plane + idx] = (float)vals[b];
+          ++k;
+        }
+      }
+      if (a.partials) {
+        acc_phi += (double)m.phi;
+        acc_T += (double)m.T;
+        acc_phip += (double)phip;
+        const double um = sqrt((double)m.u[0] * m.u[0] + (double)m.u[1] * m.u[1]);
+        acc_umax = fmax(acc_umax, um);
+        const bool bad = !(isfinite((double)m.phi) && isfinite((double)m.T) && isfinite(um) &&
+                           isfinite((double)m.p));
+        acc_bad += bad ? 1.0 : 0.0;
+      }
+    }
+  }
+  if constexpr (MODE == MODE_MACRO) {
+    if (a.partials) block_partials(acc_phi, acc_T, acc_phip, acc_umax, acc_bad, a.partials);
+  }
+}
+
+// Initialisation: populations = equilibrium - S/2 at the given fields with
+// d_t phi = 0 and div(u0 phi0) from u0; written as the pre-image of the pull
+// gather (each value goes to the slot the next gather reads it from).
+template <class Store, class Real, bool NS, bool HEAT>
+__global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, const void* phi0,
+                                                const void* T0, const void* u0, const void* p0,
+                                                int f64) {
+  using C = Codec<Real, Store>;
+  using Sc = typename ScalarOf<Store>::T;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  auto ld = [&](const void* p, int plane, int xx, int yy) -> Real {
+    const long long i = (long long)plane * a.nx * a.ny + (long long)yy * a.nx + xx;
+    return f64 ? (Real)((const double*)p)[i] : (Real)((const float*)p)[i];
+  };
+  // phi with Dirichlet ghosts, u with no-slip ghosts (x ghost then y ghost)
+  auto phi_at = [&](int xx, int yy) -> Real {
+    Real sgn = 1, add = 0;
+    if (a.wall[1] && (yy < 0 || yy >= a.ny)) {
+      add = (Real)2 * a.phi_w[1][yy < 0 ? 0 : 1];
+      sgn = -1;
+      yy = mirror(yy, a.ny);
+    } else if (!a.wall[1]) yy = wrap1(yy, a.ny);
+    Real v;
+    if (a.wall[0] && (xx < 0 || xx >= a.nx)) {
+      v = (Real)2 * a.phi_w[0][xx < 0 ? 0 : 1] - ld(phi0, 0, mirror(xx, a.nx), yy);
+    } else {
+      if (!a.wall[0]) xx = wrap1(xx, a.nx);
+      v = ld(phi0, 0, xx, yy);
+    }
+    return add + sgn * v;
+  };
+  auto u_at = [&](int comp, int xx, int yy) -> Real {
+    if (!u0) return 0;
+    Real sgn = 1;
+    if (a.wall[1] && (yy < 0 || yy >= a.ny)) {
+      sgn = -sgn;
+      yy = mirror(yy, a.ny);
+    } else if (!a.wall[1]) yy = wrap1(yy, a.ny);
+    if (a.wall[0] && (xx < 0 || xx >= a.nx)) {
+      sgn = -sgn;
+      xx = mirror(xx, a.nx);
+    } else if (!a.wall[0]) xx = wrap1(xx, a.nx);
+    return sgn * ld(u0, comp, xx, yy);
+  };
+  Real P[3][3];
+  for (int j = -1; j <= 1; ++j)
+    for (int i = -1; i <= 1; ++i) P[j + 1][i + 1] = phi_at(x + i, y + j);
+  NodeMacro<Real> m;
+  m.phi = P[1][1];
+  {
+    Real gx = 0, gy = 0, l = 0;
+    for (int i = 1; i < 9; ++i) {
+      const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+      const Real w = (Real)D2Q9::w(i);
+      const Real p = P[1 + cy][1 + cx], mm = P[1 - cy][1 - cx];
+      gx += w * (Real)cx * (Real)0.5 * (p - mm);
+      gy += w * (Real)cy * (Real)0.5 * (p - mm);
+      l += w * (p - (Real)2 * m.phi + mm);
+    }
+    m.gphi[0] = gx * (Real)3;
+    m.gphi[1] = gy * (Real)3;
+    m.gphi[2] = 0;
+    m.lphi = l * (Real)3;
+  }
+  forces(a, m.phi, m.gphi, m.lphi, m.rho, m.mu, m.F);
+  const Real inrm = rsqrt_t<Real>(m.gphi[0] * m.gphi[0] + m.gphi[1] * m.gphi[1] + a.eps2);
+  for (int d = 0; d < 3; ++d) {
+    m.grho[d] = (a.rho_g - a.rho_l) * m.gphi[d];
+    m.n[d] = m.gphi[d] * inrm;
+  }
+  m.u[0] = NS ? u_at(0, x, y) : (Real)0;
+  m.u[1] = NS ? u_at(1, x, y) : (Real)0;
+  m.u[2] = 0;
+  m.dtphi = 0;
+  m.D = 0;
+  if (HEAT && NS && u0) {
+    Real d = 0;
+    for (int i = 1; i < 9; ++i) {
+      const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+      const Real w = (Real)D2Q9::w(i);
+      const Real pp = phi_at(x + cx, y + cy), pm = phi_at(x - cx, y - cy);
+      if (cx) d += w * (Real)cx * (Real)0.5 * (u_at(0, x + cx, y + cy) * pp - u_at(0, x - cx, y - cy) * pm);
+      if (cy) d += w * (Real)cy * (Real)0.5 * (u_at(1, x + cx, y + cy) * pp - u_at(1, x - cx, y - cy) * pm);
+    }
+    m.D = d * (Real)3;
+  }
+  m.alpha = diffusivity(a, m.phi);
+  m.T = HEAT ? ld(T0, 0, x, y) : (Real)0;
+  m.q = HEAT ? production(a, m.phi, m.T, m.alpha) : (Real)0;
+  m.p = (NS && p0) ? ld(p0, 0, x, y) : (Real)0;
+  const Real cs2 = (Real)(1.0 / 3.0);
+  // eq - S/2 == the collision of (eq - S/2) with omega = 1 minus S ... write explicitly:
+  Real f[9], g[9], s[9];
+  const Real uu = m.u[0] * m.u[0] + m.u[1] * m.u[1];
+  for (int i = 0; i < 9; ++i) {
+    const Real w = (Real)D2Q9::w(i);
+    const Real G = gamma_i<D2Q9>(i, m.u, uu);
+    const Real c[3] = {(Real)D2Q9::cx(i), (Real)D2Q9::cy(i), (Real)0};
+    if (NS) {
+      Real Ff = 0;
+      for (int d = 0; d < 3; ++d) Ff += (c[d] - m.u[d]) * ((G - w) * cs2 * m.grho[d] + G * m.F[d]);
+      const Real S = Ff + w * m.rho * cs2 * m.q * a.prod_fac;
+      f[i] = w * m.p + m.rho * cs2 * (G - w) - (Real)0.5 * S;
+    }
+    const Real cn = c[0] * m.n[0] + c[1] * m.n[1];
+    const Real Fg = a.four_over_W * m.phi * ((Real)1 - m.phi) * w * cn;
+    const Real Pg = w * m.q;
+    g[i] = a.geq_cac ? m.phi * G + a.M_over_cs2g * Fg - (Real)0.5 * Pg
+                     : m.phi * G - (Real)0.5 * (Fg + Pg);
+    if (HEAT) s[i] = m.T * G - (Real)0.5 * (w * (-a.Lcp * (m.dtphi + m.D)));
+  }
+  // scatter to the pre-image slots
+  for (int i = 0; i < 9; ++i) {
+    const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+    int sx = x - cx, sy = y - cy;
+    const bool oy = cy != 0 && a.wall[1] && (sy < 0 || sy >= a.ny);
+    const bool ox = cx != 0 && !oy && a.wall[0] && (sx < 0 || sx >= a.nx);
+    const Real w = (Real)D2Q9::w(i);
+    if (oy || ox) {
+      const int j = D2Q9::opp(i);
+      const long long node = (long long)y * a.px + x;
+      Real Vg, Vs;
+      if (oy) {
+        const int side = sy < 0 ? 0 : 1;
+        Vg = a.phi_w[1][side];
+        Vs = HEAT ? a.Tw[1][side][x] : (Real)0;
+      } else {
+        const int side = sx < 0 ? 0 : 1;
+        Vg = a.phi_w[0][side];
+        Vs = HEAT ? a.Tw[0][side][y] : (Real)0;
+      }
+      if (NS) a.B[(long long)(a.off_f + j) * a.slab + node] = C::enc(f[i], w * a.ref[0], a.scale[0]);
+      a.B[(long long)(a.off_g + j) * a.slab + node] =
+          C::enc((Real)2 * w * Vg - g[i], w * a.ref[1], a.scale[1]);
+      if (HEAT)
+        a.B[(long long)(a.off_s + j) * a.slab + node] =
+            C::enc((Real)2 * w * Vs - s[i], w * a.ref[2], a.scale[2]);
+    } else {
+      if (!a.wall[0]) sx = wrap1(sx, a.nx);
+      if (!a.wall[1]) sy = wrap1(sy, a.ny);
+      const long long node = (long long)sy * a.px + sx;
+      if (NS) a.B[(long long)(a.off_f + i) * a.slab + node] = C::enc(f[i], w * a.ref[0], a.scale[0]);
+      a.B[(long long)(a.off_g + i) * a.slab + node] = C::enc(g[i], w * a.ref[1], a.scale[1]);
+      if (HEAT) a.B[(long long)(a.off_s + i) * a.slab + node] = C::enc(s[i], w * a.ref[2], a.scale[2]);
+    }
+  }
+  const long long node = (long long)y * a.px + x;
+  a.B_phip[node] = (Sc)m.phi;
+  a.B_qp[node] = (Sc)m.q;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <class Store, class Real>
+static hipError_t launch_step2d_t(const KArgs<Real, Store>& a, int ns, int heat, int mode,
+                                  hipStream_t st) {
+  const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + TY2 - 1) / TY2);
+  dim3 grid(tiles), block(NT2);
+#define LBM_L(NSV, HV, MV) \
+  hipLaunchKernelGGL((k_step2d<Store, Real, NSV, HV, MV>), grid, block, 0, st, a)
+  if (mode == MODE_STEP) {
+    if (ns && heat) LBM_L(true, true, MODE_STEP);
+    else if (ns) LBM_L(true, false, MODE_STEP);
+    else if (heat) LBM_L(false, true, MODE_STEP);
+    else LBM_L(false, false, MODE_STEP);
+  } else {
+    if (ns && heat) LBM_L(true, true, MODE_MACRO);
+    else if (ns) LBM_L(true, false, MODE_MACRO);
+    else if (heat) LBM_L(false, true, MODE_MACRO);
+    else LBM_L(false, false, MODE_MACRO);
+  }
+#undef LBM_L
+  return hipGetLastError();
+}
+
+template <class Store, class Real>
+static hipError_t launch_init2d_t(const KArgs<Real, Store>& a, int ns, int heat, const void* phi0,
+                                  const void* T0, const void* u0, const void* p0, int f64,
+                                  hipStream_t st) {
+  dim3 block(256), grid((a.nx + 255) / 256, a.ny);
+#define LBM_I(NSV, HV) \
+  hipLaunchKernelGGL((k_init2d<Store, Real, NSV, HV>), grid, block, 0, st, a, phi0, T0, u0, p0, f64)
+  if (ns && heat) LBM_I(true, true);
+  else if (ns) LBM_I(true, false);
+  else if (heat) LBM_I(false, true);
+  else LBM_I(false, false);
+#undef LBM_I
+  return hipGetLastError();
+}
+
+int step2d_blocks(int nx, int ny) { return ((nx + TX2 - 1) / TX2) * ((ny + TY2 - 1) / TY2); }
+
+#define LBM_INST(STORE, REAL)                                                                 \
+  hipError_t launch_step2d(const KArgs<REAL, STORE>& a, int ns, int heat, int mode,           \
+                           hipStream_t st) {                                                  \
+    return launch_step2d_t<STORE, REAL>(a, ns, heat, mode, st);                               \
+  }                                                                                           \
+  hipError_t launch_init2d(const KArgs<REAL, STORE>& a, int ns, int heat, const void* phi0,   \
+                           const void* T0, const void* u0, const void* p0, int f64,           \
+                           hipStream_t st) {                                                  \
+    return launch_init2d_t<STORE, REAL>(a, ns, heat, phi0, T0, u0, p0, f64, st);              \
+  }
+LBM_INST(double, double)
+LBM_INST(float, float)
+LBM_INST(__half, float)
+LBM_INST(__hip_bfloat16, float)
+#undef LBM_INST
+
+}  // namespace lbm

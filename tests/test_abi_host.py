@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/lbm.h declares, and rejects invalid parameter sets with
+the documented status codes before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2003_06342_amd import inputs as I
+from paper_2003_06342_amd import lbm
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lbm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lbm.LIB_PATH):
+        pytest.fail("liblbm.so is not built (run __graft_entry__.build())")
+    return lbm.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "lbm_step" in names and "lbm_create" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_error_string(lib):
+    assert b"gfx950" in lib.lbm_version()
+    assert lib.lbm_last_error() is not None
+
+
+def test_struct_layout_matches_header():
+    # the Python mirror of lbm_params must have the C size (same field order)
+    assert C.sizeof(lbm.lbm_params) == 4 * 9 + 4 + 8 * 13 + 8 * 6 + 4 * 3 + 4 + 8 * 12 + 8
+
+
+def _status(prm, storage="f32"):
+    lib = lbm.load_library()
+    p = lbm.make_params(prm, storage)
+    n = C.c_size_t()
+    return lib.lbm_workspace_size(C.byref(p), C.byref(n)), n.value
+
+
+def test_workspace_size_valid(lib):
+    prm = I.film2d_params(130, 66)
+    st, n = _status(prm)
+    assert st == lbm.LBM_OK
+    # 27 populations x 2 buffers x pitch 192 x 66 x 4 B at least
+    assert n >= 2 * 27 * 192 * 66 * 4
+
+
+@pytest.mark.parametrize("key,val", [("nu_l", 0.0), ("mobility", -1.0), ("alpha_g", 0.0),
+                                     ("W", 0.0), ("rho_g", 0.0)])
+def test_rejects_nonpositive_transport(lib, key, val):
+    prm = I.film2d_params(64, 32)
+    prm[key] = val
+    st, _ = _status(prm)
+    assert st == lbm.LBM_E_INVAL
+    assert key.encode() in lib.lbm_last_error()
+
+
+def test_rejects_bad_lattice_and_dims(lib):
+    prm = I.film2d_params(64, 32)
+    prm["lat_g"] = "D3Q7"
+    assert _status(prm)[0] == lbm.LBM_E_UNSUPPORTED
+    prm = I.film2d_params(64, 32)
+    prm["nz"] = 2
+    assert _status(prm)[0] == lbm.LBM_E_INVAL
+
+
+def test_phase_change_needs_heat(lib):
+    p = lbm.make_params(I.film2d_params(16, 16), "f32")
+    p.flags = lbm.LBM_NS | lbm.LBM_PHASE_CHANGE
+    n = C.c_size_t()
+    assert lib.lbm_workspace_size(C.byref(p), C.byref(n)) == lbm.LBM_E_INVAL
+
+
+def test_null_arguments(lib):
+    assert lib.lbm_step(None, 1) == lbm.LBM_E_INVAL
+    assert lib.lbm_sync(None) == lbm.LBM_E_INVAL
+    out = C.c_void_p()
+    p = lbm.make_params(I.film2d_params(16, 16), "f32")
+    assert lib.lbm_create(C.byref(p), None, 0, None, C.byref(out)) == lbm.LBM_E_INVAL
+    assert out.value is None

@@ -1,0 +1,138 @@
+"""GPU parity of the 2-D HIP path (through the C ABI) against the FP64
+oracle on the same seeded inputs.
+
+Bars: FP64 storage within 1e-10 relative L2 (rounding order only); FP32
+storage within 1e-5 relative L2 per field (phi, T, |u|; p about its mean is
+reported with a looser bar because its mean drifts in a closed box and the
+FP32 gauge carries that drift)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2003_06342_amd import inputs as I
+from tests._parity import compare, gpu_run, need_gpu, oracle_run, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+def film_case(nx, ny, h0, amp, seed=0, **kw):
+    prm = I.film2d_params(nx, ny, **kw)
+    phi0, T0, _ = I.film2d_fields(prm, seed=seed, h0=h0, amp=amp)
+    return prm, phi0, T0
+
+
+def _check(name, prm, phi0, T0, nsteps, storage, tol, ptol=None, **kw):
+    need_gpu()
+    say(f"[parity] {name}: {prm['nx']}x{prm['ny']} storage={storage} steps={nsteps}")
+    ref = oracle_run(prm, phi0, T0, nsteps, Tw_face=kw.get("Tw_face"))
+    gpu = gpu_run(prm, phi0, T0, nsteps, storage, **kw)
+    errs = compare(gpu, ref)
+    say(f"[parity] {name}: errors {errs}")
+    for k in ("phi", "T", "umag"):
+        if k == "T" and not prm["heat"]:
+            continue
+        if k == "umag" and not prm["ns"]:
+            continue
+        assert errs[k] <= tol, (k, errs)
+    if prm["ns"]:
+        assert errs["p"] <= (ptol if ptol is not None else tol), errs
+    return errs, gpu, ref
+
+
+def test_init_round_trip_f64():
+    need_gpu()
+    prm, phi0, T0 = film_case(130, 66, 12.0, 2.0)
+    gpu = gpu_run(prm, phi0, T0, 0, "f64")
+    assert np.abs(gpu["phi"] - phi0).max() < 1e-14
+    assert np.abs(gpu["T"] - T0).max() < 1e-14
+    assert np.abs(gpu["ux"]).max() < 1e-15 and np.abs(gpu["p"]).max() < 1e-15
+
+
+def test_film_f64_ragged_tiles():
+    """130 x 66: ragged in x and y, y walls (bounce-back / anti-bounce-back)."""
+    prm, phi0, T0 = film_case(130, 66, 12.0, 2.0)
+    prm["gravity"] = [0.0, -2e-5, 0.0]
+    _check("film_f64", prm, phi0, T0, 60, "f64", 1e-10)
+
+
+def test_film_f32_ragged_tiles():
+    prm, phi0, T0 = film_case(130, 66, 12.0, 2.0)
+    prm["gravity"] = [0.0, -2e-5, 0.0]
+    _check("film_f32", prm, phi0, T0, 200, "f32", 1e-5, ptol=1e-4)
+
+
+def test_drop_f64_conserves_mass():
+    """Static drop (periodic, heat off): parity and sum(phi) conservation on
+    the GPU's FP64 diagnostics."""
+    need_gpu()
+    prm = I.drop_params(96)
+    phi0, T0 = I.drop_fields(prm, radius=24.0)
+    errs, gpu, ref = _check("drop_f64", prm, phi0, None, 150, "f64", 1e-10)
+    m0 = float(phi0.sum())
+    assert abs(gpu["diag"]["mass"] - m0) / m0 < 1e-13
+    assert gpu["diag"]["mass"] == pytest.approx(ref["diag"]["mass"], rel=1e-13)
+
+
+def test_stefan_x_walls_f64():
+    """NS off, anti-bounce-back walls on x, periodic y with ny = 3."""
+    p = I.base_params(dim=2, nx=150, ny=3, ns=False, heat=True, phase_change=True,
+                      alpha_l=0.14, alpha_g=0.014, mobility=0.08, W=3.0, L_over_cp=1.0,
+                      theta_I=0.05)
+    p["bc"] = ["wall", "periodic", "periodic"]
+    p["phi_wall"] = [[0.0, 1.0], [0, 0], [0, 0]]
+    p["T_wall"] = [[-0.3, 0.3], [0, 0], [0, 0]]
+    x = np.arange(150) + 0.5
+    phi0 = np.repeat((0.5 * (1 + np.tanh(2 * x / 3.0)))[None, None, :], 3, axis=1)
+    T0 = np.full((1, 3, 150), 0.3)
+    _check("stefan_f64", p, phi0, T0, 300, "f64", 1e-10)
+
+
+def test_periodic_full_coupling_f64_flags():
+    """Periodic box, all couplings, linear viscosity and the CAC equilibrium
+    form; enthalpy invariant on the GPU."""
+    need_gpu()
+    p = I.base_params(dim=2, nx=70, ny=50, visc_linear=True, geq_cac=True, **I.FB)
+    p["gravity"] = [0.0, -1e-4, 0.0]
+    phi0, T0 = I.random_smooth_fields(p, seed=11, T_amp=0.5)
+    errs, gpu, ref = _check("periodic_flags_f64", p, phi0, T0, 80, "f64", 1e-10)
+    assert gpu["diag"]["enthalpy"] == pytest.approx(ref["diag"]["enthalpy"], rel=1e-12)
+
+
+def test_wall_temperature_row_f64():
+    """Per-node wall temperature T_w(x) on the heated floor."""
+    prm, phi0, T0 = film_case(96, 40, 8.0, 1.5)
+    Tw = I.wall_T_row(96, seed=3)
+    _check("wall_row_f64", prm, phi0, T0, 60, "f64", 1e-10, Tw_face=(1, 0, Tw))
+
+
+def test_checkpoint_resume_bitwise():
+    need_gpu()
+    from paper_2003_06342_amd import lbm
+    prm, phi0, T0 = film_case(70, 40, 8.0, 1.5)
+    a = lbm.Sim(prm, "f32").init(phi0, T0)
+    a.step(30)
+    blob = a.get_state()
+    a.step(20)
+    fa = {k: v.cpu().numpy() for k, v in a.fields().items()}
+    b = lbm.Sim(prm, "f32")
+    b.set_state(blob)
+    b.step(20)
+    fb = {k: v.cpu().numpy() for k, v in b.fields().items()}
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+
+
+def test_split_steps_equal_one_call():
+    need_gpu()
+    prm, phi0, T0 = film_case(64, 48, 8.0, 1.5)
+    one = gpu_run(prm, phi0, T0, 25, "f32")
+    many = gpu_run(prm, phi0, T0, 25, "f32", chunks=[1, 7, 3, 14])
+    for k in ("phi", "T", "ux", "p"):
+        assert np.array_equal(one[k], many[k])
+
+
+def test_film_f32_1000_steps():
+    """The FP32 bar: <= 1e-5 relative L2 vs the FP64 oracle after 1000 steps
+    (film recipe on 192 x 128, several tiles and walls)."""
+    prm, phi0, T0 = film_case(192, 128, 24.0, 3.0)
+    _check("film_f32_1000", prm, phi0, T0, 1000, "f32", 1e-5, ptol=1e-4)
