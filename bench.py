@@ -1,0 +1,164 @@
+"""Throughput benchmark of the fused phase-change LBM step on one MI355X.
+
+Headline workload: 2-D film boiling on 1024 x 2048 nodes, D2Q9 for f, g and
+s, FP32 storage (the film-boiling parameter set of the paper's Sec. 5.1 in
+lattice units; seeded synthetic initial film).  A step is one fused pass of
+the whole hot path over the grid.  Prints ONE JSON line.
+
+  value      MLUPS = nodes * steps / seconds / 1e6 (the paper's metric, Sec. 3.5)
+  roofline   HBM-bound: algorithmic bytes per node update (populations read
+             once and written once plus the lagged phi and q) over the kernel
+             time measured with HIP events on the launch stream
+  cpu_baseline  the FP64 oracle timed on a bounded sample of the same
+             workload on this host's cores
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS + % HBM roofline, FP32 & FP16-store vs FP64 oracle error; adjoint/fwd"
+
+
+def bytes_per_node(dim: int, q_total: int, storage: str) -> int:
+    """Algorithmic bytes per node update: every population read once and
+    written once, plus phi_prev and q_prev read and written."""
+    pe = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}[storage]
+    se = 8 if storage == "f64" else 4
+    return q_total * pe * 2 + 2 * se * 2
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2003_06342_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def time_variant(prm, fields, storage, steps, warmup):
+    import torch
+    from paper_2003_06342_amd import lbm
+    sim = lbm.Sim(prm, storage)
+    sim.init(*fields)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    # per-launch kernel time with HIP events on the launch stream
+    nev = min(steps, 50)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(nev)]
+    for a, b in evs:
+        a.record(stream)
+        sim.step(1)
+        b.record(stream)
+    torch.cuda.synchronize()
+    kern_ms = sum(a.elapsed_time(b) for a, b in evs) / nev
+    # whole-job timing of exactly `steps` steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    diag = sim.diagnostics(check=False)
+    sim.close()
+    n = prm["nx"] * prm["ny"] * prm["nz"]
+    return dict(ms_per_step=1e3 * dt / steps, mlups=n * steps / dt / 1e6, kernel_ms=kern_ms,
+                nodes=n, finite=diag["nonfinite"] == 0)
+
+
+def cpu_baseline(prm, fields, budget_s=20.0):
+    """FP64 oracle on the same grid for as many whole steps as fit ~budget_s."""
+    import torch
+    from oracle.lbm_oracle import Model
+    M = Model(prm)
+    st = M.init(*fields)
+    t0 = time.perf_counter()
+    st = M.step(st)
+    one = time.perf_counter() - t0
+    k = max(1, min(20, int(budget_s / max(one, 1e-3)) - 1))
+    t0 = time.perf_counter()
+    for _ in range(k):
+        st = M.step(st)
+    dt = time.perf_counter() - t0
+    n = prm["nx"] * prm["ny"] * prm["nz"]
+    return dict(value=n * k / dt / 1e6, unit="MLUPS", cores=torch.get_num_threads(), kind="oracle",
+                sample=f"{k} FP64 oracle steps of the full {prm['nx']}x{prm['ny']} film grid "
+                       f"after 1 untimed step ({dt:.1f} s)")
+
+
+def traffic_entry(name: str, nodes: int):
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_hash") != kernel_sources_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build targets one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU slab decomposition is design-only)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2003_06342_amd import inputs as I
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+
+    nx, ny = 1024, 2048
+    prm = I.film2d_params(nx, ny)
+    phi0, T0, _ = I.film2d_fields(prm, seed=0, h0=64.0, amp=4.0)
+    fields = (phi0, T0)
+    head = time_variant(prm, fields, "f32", args.steps, args.warmup)
+    bpn = bytes_per_node(2, 27, "f32")
+    achieved = bpn * head["nodes"] / (head["kernel_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(head["mlups"], 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "2-D film boiling, D2Q9 f+g+s, FP32 populations",
+                   "nx": nx, "ny": ny, "global_batch": nx * ny, "seq_len": 1,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_entry("k_step2d_film1024x2048_f32", head["nodes"]),
+                     "kernel": "k_step2d<float,float,NS,HEAT,STEP>",
+                     "bytes_per_node": bpn, "kernel_ms": round(head["kernel_ms"], 5)},
+        "context": {"paper_K80_MLUPS_1024x1024": 80.96, "paper_Xeon16c_MLUPS_1024x1024": 11.97},
+    }
+    if not head["finite"]:
+        out["warning"] = "non-finite values after the timed run"
+    if not args.no_variants:
+        var = {}
+        for st in ("f64", "f16dev", "bf16dev"):
+            r = time_variant(prm, fields, st, max(20, args.steps // 4), 5)
+            b = bytes_per_node(2, 27, st)
+            var[f"film2d_{st}"] = dict(mlups=round(r["mlups"], 1), kernel_ms=round(r["kernel_ms"], 5),
+                                       hbm_frac=round(b * r["nodes"] / (r["kernel_ms"] * 1e-3) / 1e9
+                                                      / HBM_PEAK_GBS, 4))
+        out["variants"] = var
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prm, fields)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -103,7 +103,7 @@ typedef struct {
   int32_t bc[3];                 /* LBM_BC_* per axis x, y, z                 */
   double phi_wall[3][2];         /* [axis][lo, hi] anti-bounce-back phi       */
   double T_wall[3][2];           /* [axis][lo, hi] anti-bounce-back T         */
-  double eps_n;                  /* regularisation of n = grad phi / |grad phi| (0 -> 1e-9) */
+  double eps_n;                  /* n = grad phi / sqrt(|grad phi|^2 + eps_n^2) (0 -> 1e-3) */
 } lbm_params;
 
 /* Bytes of device workspace lbm_create needs for these parameters

@@ -39,7 +39,9 @@ same ones):
   R7  d_t phi = phi^n - phi^{n-1} (0 at the first step).
   R8  div(u phi) = sum_a of the a-th component of the Eq. Grad stencil applied
       to u_a phi.
-  R9  n = grad(phi) / sqrt(|grad(phi)|^2 + eps^2), eps = 1e-9.
+  R9  n = grad(phi) / sqrt(|grad(phi)|^2 + eps^2), eps = 1e-3: far below
+      interface gradients (~1/W), far above round-off gradients in the bulk
+      phases, where a smaller eps turns round-off into O(phi(1-phi)) forcing.
   R10 alpha(phi) = (1 - phi) alpha_l + phi alpha_g, used for tau_s and in q.
   R12 init: populations = equilibrium - S/2 at the initial fields with
       d_t phi = 0 and div(u phi) from u0, so the moments return the inputs.
@@ -189,7 +191,7 @@ class Model:
         self.M = float(prm["mobility"])
         self.grav = [float(v) for v in prm["gravity"]]
         self.body = [float(v) for v in prm.get("body_force", (0.0, 0.0, 0.0))]
-        self.eps = float(prm.get("eps_n", 1e-9))
+        self.eps = float(prm.get("eps_n", 1e-3))
         # Eq. Def_K-H
         self.K = 1.5 * self.W * self.sigma
         self.H = 12.0 * self.sigma / self.W

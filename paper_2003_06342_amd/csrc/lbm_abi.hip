@@ -167,7 +167,7 @@ KArgs<Real, Store> make_args(const lbm_ctx* c) {
   a.K = (Real)(1.5 * p.W * p.sigma);          // Eq. Def_K-H
   a.H = (Real)(12.0 * p.sigma / p.W);
   a.four_over_W = (Real)(4.0 / p.W);
-  const double eps = p.eps_n > 0 ? p.eps_n : 1e-9;
+  const double eps = p.eps_n > 0 ? p.eps_n : 1e-3;
   a.eps2 = (Real)(eps * eps);
   for (int d = 0; d < 3; ++d) {
     a.grav[d] = (Real)p.gravity[d];

@@ -45,7 +45,7 @@ _BASE = dict(
     bc=["periodic", "periodic", "periodic"],
     phi_wall=[[0.0, 0.0], [0.0, 0.0], [0.0, 0.0]],
     T_wall=[[0.0, 0.0], [0.0, 0.0], [0.0, 0.0]],
-    eps_n=1e-9,
+    eps_n=1e-3,
 )
 
 
