@@ -160,10 +160,15 @@ class Model:
     ``prm`` is the plain parameter dict built by the workload module.
     ``T_wall_faces`` optionally replaces the scalar wall temperature of a
     face by a per-node face array: key (axis, side) -> tensor broadcastable
-    to [nz, ny, nx] (size 1 along ``axis``)."""
+    to [nz, ny, nx] (size 1 along ``axis``).
 
-    def __init__(self, prm: dict, T_wall_faces: Optional[dict] = None):
+    ``dtype`` is float64 for the oracle proper.  float32 evaluates the same
+    arithmetic in single precision; it is used only to measure the rounding
+    floor that any FP32 implementation of the scheme has on a given case."""
+
+    def __init__(self, prm: dict, T_wall_faces: Optional[dict] = None, dtype=F64):
         self.prm = prm
+        self.dt = dtype
         self.dim = int(prm["dim"])
         self.shape = (int(prm["nz"]), int(prm["ny"]), int(prm["nx"]))
         self.ns = bool(prm["ns"])
@@ -197,11 +202,11 @@ class Model:
         self.H = 12.0 * self.sigma / self.W
         self.wall = [prm["bc"][a] == "wall" for a in range(3)]
         self.phi_w = [[float(prm["phi_wall"][a][s]) for s in range(2)] for a in range(3)]
-        self.T_w = [[torch.tensor(float(prm["T_wall"][a][s]), dtype=F64)
+        self.T_w = [[torch.tensor(float(prm["T_wall"][a][s]), dtype=self.dt)
                      for s in range(2)] for a in range(3)]
         if T_wall_faces:
             for (a, s), arr in T_wall_faces.items():
-                self.T_w[a][s] = torch.as_tensor(arr, dtype=F64)
+                self.T_w[a][s] = torch.as_tensor(arr, dtype=self.dt)
 
     # -- closures (Sec. 2) --------------------------------------------------
 
@@ -255,7 +260,7 @@ class Model:
         """Eqs. DerivDirec_Grad and Grad: (1/c_s^2) sum_i w_i e_i [v(x+e_i) -
         v(x-e_i)] / 2 over the stencil lattice (R2, R3)."""
         L = self.Lst
-        out = [torch.zeros(self.shape, dtype=F64) for _ in range(3)]
+        out = [torch.zeros(self.shape, dtype=self.dt) for _ in range(3)]
         for i in range(1, L.Q):
             e = L.c[i]
             dd = 0.5 * (self._shift(padded, e) - self._shift(padded, tuple(-x for x in e)))
@@ -267,7 +272,7 @@ class Model:
     def laplacian(self, padded, centre):
         """Eqs. DerivDirect_Laplacian and Laplacian."""
         L = self.Lst
-        out = torch.zeros(self.shape, dtype=F64)
+        out = torch.zeros(self.shape, dtype=self.dt)
         for i in range(1, L.Q):
             e = L.c[i]
             out = out + L.w[i] * (self._shift(padded, e) - 2.0 * centre
@@ -289,7 +294,7 @@ class Model:
 
     def divergence(self, u, phi_padded):
         """div(u phi) with the central directional-derivative stencil (R8)."""
-        D = torch.zeros(self.shape, dtype=F64)
+        D = torch.zeros(self.shape, dtype=self.dt)
         for a in range(3):
             prod = self.ghost_pad(u[a], "anti") * phi_padded
             D = D + self.grad(prod)[a]
@@ -321,13 +326,13 @@ class Model:
             for a in range(3):
                 m1 = sum(st.f[i] * Lf.c[i][a] for i in range(Lf.Q) if Lf.c[i][a] != 0)
                 if isinstance(m1, int):
-                    m1 = torch.zeros(self.shape, dtype=F64)
+                    m1 = torch.zeros(self.shape, dtype=self.dt)
                 u.append((m1 / Lf.cs2 + 0.5 * F[a]) / rho)
         elif u_prescribed is not None:
-            u = [torch.as_tensor(u_prescribed[a], dtype=F64) * torch.ones(self.shape, dtype=F64)
+            u = [torch.as_tensor(u_prescribed[a], dtype=self.dt) * torch.ones(self.shape, dtype=self.dt)
                  for a in range(3)]
         else:
-            u = [torch.zeros(self.shape, dtype=F64) for _ in range(3)]
+            u = [torch.zeros(self.shape, dtype=self.dt) for _ in range(3)]
         # S4: time derivative (R7) and divergence (R8)
         dtphi = phi - st.phi_prev
         alpha = self.diffusivity(phi)
@@ -336,8 +341,8 @@ class Model:
             # S5: Eq. Moment_Temp
             T = st.s.sum(0) - 0.5 * self.Lcp * (dtphi + D)
         else:
-            D = torch.zeros(self.shape, dtype=F64)
-            T = torch.zeros(self.shape, dtype=F64)
+            D = torch.zeros(self.shape, dtype=self.dt)
+            T = torch.zeros(self.shape, dtype=self.dt)
         # S6: Eq. ProductionRate
         q = self.production(phi, T, alpha)
         # S7: Eq. Pressure (R18)
@@ -348,7 +353,7 @@ class Model:
             p = st.f.sum(0) + 0.5 * (cs2 * udr + rho * cs2 * mdot
                                      * (1.0 / self.rho_g - 1.0 / self.rho_l))
         else:
-            p = torch.zeros(self.shape, dtype=F64)
+            p = torch.zeros(self.shape, dtype=self.dt)
         return Macros(phi, gphi, lphi, n, mu, rho, grho, F, u, dtphi, D, T, q, p,
                       alpha, self.viscosity(phi))
 
@@ -361,7 +366,7 @@ class Model:
         for i in range(L.Q):
             cu = sum(L.c[i][a] * u[a] for a in range(3) if L.c[i][a] != 0)
             if isinstance(cu, int):
-                cu = torch.zeros(self.shape, dtype=F64)
+                cu = torch.zeros(self.shape, dtype=self.dt)
             out.append(L.w[i] * (1.0 + cu / L.cs2 + cu * cu / (2.0 * L.cs2 ** 2)
                                  - uu / (2.0 * L.cs2)))
         return out
@@ -469,7 +474,7 @@ class Model:
     def step(self, st: State, u_prescribed=None) -> State:
         m = self.macros(st, u_prescribed)
         pf, pg, ps = self.collide(st, m)
-        phiw = [[torch.tensor(v, dtype=F64) for v in side] for side in self.phi_w]
+        phiw = [[torch.tensor(v, dtype=self.dt) for v in side] for side in self.phi_w]
         nf = self.stream(pf, self.Lf, "bb") if self.ns else None
         ng = self.stream(pg, self.Lg, "abb", phiw)
         ns_ = self.stream(ps, self.Ls, "abb", self.T_w) if self.heat else None
@@ -483,15 +488,15 @@ class Model:
     # -- initialisation (R12) ---------------------------------------------------
 
     def init(self, phi0, T0=None, u0=None, p0=None) -> State:
-        phi = torch.as_tensor(phi0, dtype=F64).reshape(self.shape)
-        T = (torch.zeros(self.shape, dtype=F64) if (T0 is None or not self.heat)
-             else torch.as_tensor(T0, dtype=F64).reshape(self.shape))
-        u = ([torch.zeros(self.shape, dtype=F64) for _ in range(3)] if u0 is None
-             else [torch.as_tensor(u0[a], dtype=F64).reshape(self.shape) for a in range(3)])
+        phi = torch.as_tensor(phi0, dtype=self.dt).reshape(self.shape)
+        T = (torch.zeros(self.shape, dtype=self.dt) if (T0 is None or not self.heat)
+             else torch.as_tensor(T0, dtype=self.dt).reshape(self.shape))
+        u = ([torch.zeros(self.shape, dtype=self.dt) for _ in range(3)] if u0 is None
+             else [torch.as_tensor(u0[a], dtype=self.dt).reshape(self.shape) for a in range(3)])
         if not self.ns and u0 is None:
-            u = [torch.zeros(self.shape, dtype=F64) for _ in range(3)]
-        p = (torch.zeros(self.shape, dtype=F64) if p0 is None
-             else torch.as_tensor(p0, dtype=F64).reshape(self.shape))
+            u = [torch.zeros(self.shape, dtype=self.dt) for _ in range(3)]
+        p = (torch.zeros(self.shape, dtype=self.dt) if p0 is None
+             else torch.as_tensor(p0, dtype=self.dt).reshape(self.shape))
         P = self.ghost_pad(phi, "phi")
         gphi = self.grad(P)
         lphi = self.laplacian(P, phi)
@@ -500,9 +505,9 @@ class Model:
         mu, rho, F = self.forces(phi, gphi, lphi)
         grho = [(self.rho_g - self.rho_l) * gphi[a] for a in range(3)]
         alpha = self.diffusivity(phi)
-        D = self.divergence(u, P) if self.heat else torch.zeros(self.shape, dtype=F64)
-        q = self.production(phi, T, alpha) if self.heat else torch.zeros(self.shape, dtype=F64)
-        zero = torch.zeros(self.shape, dtype=F64)
+        D = self.divergence(u, P) if self.heat else torch.zeros(self.shape, dtype=self.dt)
+        q = self.production(phi, T, alpha) if self.heat else torch.zeros(self.shape, dtype=self.dt)
+        zero = torch.zeros(self.shape, dtype=self.dt)
         m = Macros(phi, gphi, lphi, n, mu, rho, grho, F, u, zero, D, T, q, p, alpha,
                    self.viscosity(phi))
         f = g = s = None

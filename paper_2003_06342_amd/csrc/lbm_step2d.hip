@@ -21,7 +21,7 @@
 
 namespace lbm {
 
-constexpr int TX2 = 64, TY2 = 16, NT2 = 256;
+constexpr int TX2 = 64, TY2 = 32, NT2 = 256;
 constexpr int R1X = TX2 + 4, R1Y = TY2 + 4;   // phi region (halo 2)
 constexpr int R2X = TX2 + 2, R2Y = TY2 + 2;   // u region (halo 1)
 
@@ -29,12 +29,26 @@ constexpr int R2X = TX2 + 2, R2Y = TY2 + 2;   // u region (halo 1)
 // (x, y).  A link whose source lies beyond a wall reflects at the node:
 // bounce-back for f, anti-bounce-back -v_{i'} + 2 w_i V_w for g and s
 // (Sec. 3.3).  The y wall takes precedence over the x wall at corners.
-template <class Lat, int FAM, class Real, class Store>
+// FAST: the caller guarantees that no source node of this tile lies beyond
+// a wall or across a periodic seam, so every pull is the uniform plane
+// pointer shifted by -(c_x + c_y px) and indexed by the node's lane offset.
+template <class Lat, int FAM, bool FAST = false, class Real, class Store>
 __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real* v) {
   using C = Codec<Real, Store>;
   const int off = FAM == 0 ? a.off_f : (FAM == 1 ? a.off_g : a.off_s);
   const Real ref = a.ref[FAM], inv = a.inv_scale[FAM];
-  const long long node = (long long)y * a.px + x;
+  // uniform plane base (scalar registers) + 32-bit lane offset
+  const Store* __restrict__ base = a.A + (size_t)off * (size_t)a.slab;
+  const unsigned node = (unsigned)(y * a.px + x);
+  if constexpr (FAST) {
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i) {
+      const Store* __restrict__ p =
+          base + (size_t)i * (size_t)a.slab - (ptrdiff_t)(Lat::cx(i) + Lat::cy(i) * a.px);
+      v[i] = C::dec(p[node], (Real)Lat::w(i) * ref, inv);
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
     const int cx = Lat::cx(i), cy = Lat::cy(i);
@@ -44,7 +58,7 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
     const Real wref = (Real)Lat::w(i) * ref;
     if (oy || ox) {
       const int j = Lat::opp(i);
-      Real r = C::dec(a.A[(long long)(off + j) * a.slab + node], wref, inv);
+      Real r = C::dec((base + (size_t)j * (size_t)a.slab)[node], wref, inv);
       if (FAM != 0) {
         Real V;
         if (oy) {
@@ -60,9 +74,21 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
     } else {
       if (cx != 0 && !a.wall[0]) sx = wrap1(sx, a.nx);
       if (cy != 0 && !a.wall[1]) sy = wrap1(sy, a.ny);
-      v[i] = C::dec(a.A[(long long)(off + i) * a.slab + (long long)sy * a.px + sx], wref, inv);
+      v[i] = C::dec((base + (size_t)i * (size_t)a.slab)[(unsigned)(sy * a.px + sx)], wref, inv);
     }
   }
+}
+
+// Store the Q post-collision populations of one family at `node` of B.
+template <class Lat, class Real, class Store>
+__device__ inline void store_family(const KArgs<Real, Store>& a, int off, int fam, unsigned node,
+                                    const Real* v) {
+  using C = Codec<Real, Store>;
+  Store* __restrict__ base = a.B + (size_t)off * (size_t)a.slab;
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i)
+    (base + (size_t)i * (size_t)a.slab)[node] =
+        C::enc(v[i], (Real)Lat::w(i) * a.ref[fam], a.scale[fam]);
 }
 
 // Directional-derivative gradient and Laplacian (Eqs. DerivDirec_Grad, Grad,
@@ -116,22 +142,11 @@ __device__ inline bool to_domain(int& g, int n, int wall) {
 // Mirror of a ghost coordinate across the half-way wall (-1 <-> 0, n <-> n-1).
 __device__ inline int mirror(int g, int n) { return g < 0 ? -1 - g : 2 * n - 1 - g; }
 
-template <class Store, class Real, bool NS, bool HEAT, int MODE>
-__global__ __launch_bounds__(NT2) void k_step2d(const KArgs<Real, Store> a) {
+template <class Store, class Real, bool NS, bool HEAT, int MODE, bool FAST>
+__device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*sphi)[R1X],
+                                            Real (*sux)[R2X], Real (*suy)[R2X], int x0, int y0) {
   using C = Codec<Real, Store>;
   using Sc = typename ScalarOf<Store>::T;
-  __shared__ Real sphi[R1Y][R1X];
-  __shared__ Real sux[R2Y][R2X];
-  __shared__ Real suy[R2Y][R2X];
-
-  const int tiles_x = (a.nx + TX2 - 1) / TX2;
-  const int ntiles = tiles_x * ((a.ny + TY2 - 1) / TY2);
-  // XCD-aware order: hardware deals blocks to the 8 XCDs round-robin; give
-  // each XCD a contiguous band of tiles so neighbouring tiles share an L2.
-  int t = blockIdx.x;
-  const int full = (ntiles / 8) * 8;
-  if (t < full) t = (t % 8) * (full / 8) + t / 8;
-  const int x0 = (t % tiles_x) * TX2, y0 = (t / tiles_x) * TY2;
   const int tid = threadIdx.x;
 
   // ---- phase 1: phi on the tile + 2-halo --------------------------------
@@ -139,18 +154,18 @@ __global__ __launch_bounds__(NT2) void k_step2d(const KArgs<Real, Store> a) {
     const int ry = k / R1X, rx = k - ry * R1X;
     int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
     Real v = 0;
-    if (to_domain(gx, a.nx, a.wall[0]) && to_domain(gy, a.ny, a.wall[1])) {
+    if (FAST || (to_domain(gx, a.nx, a.wall[0]) && to_domain(gy, a.ny, a.wall[1]))) {
       Real g[9];
-      gather2d<D2Q9, 1>(a, gx, gy, g);
+      gather2d<D2Q9, 1, FAST>(a, gx, gy, g);
       Real s = 0;
 #pragma unroll
       for (int i = 0; i < 9; ++i) s += g[i];
-      v = s + (Real)0.5 * (Real)a.A_qp[(long long)gy * a.px + gx];
+      v = s + (Real)0.5 * (Real)a.A_qp[(unsigned)(gy * a.px + gx)];
     }
     sphi[ry][rx] = v;
   }
   __syncthreads();
-  if (a.wall[0]) {   // x ghosts first, then y ghosts (corners compose)
+  if (!FAST && a.wall[0]) {   // x ghosts first, then y ghosts (corners compose)
     for (int k = tid; k < R1X * R1Y; k += NT2) {
       const int ry = k / R1X, rx = k - ry * R1X;
       const int gx = x0 - 2 + rx;
@@ -161,7 +176,7 @@ __global__ __launch_bounds__(NT2) void k_step2d(const KArgs<Real, Store> a) {
     }
     __syncthreads();
   }
-  if (a.wall[1]) {
+  if (!FAST && a.wall[1]) {
     for (int k = tid; k < R1X * R1Y; k += NT2) {
       const int ry = k / R1X, rx = k - ry * R1X;
       const int gy = y0 - 2 + ry;
@@ -179,12 +194,12 @@ __global__ __launch_bounds__(NT2) void k_step2d(const KArgs<Real, Store> a) {
       const int ry = k / R2X, rx = k - ry * R2X;
       int gx = x0 - 1 + rx, gy = y0 - 1 + ry;
       Real ux = 0, uy = 0;
-      if (to_domain(gx, a.nx, a.wall[0]) && to_domain(gy, a.ny, a.wall[1])) {
+      if (FAST || (to_domain(gx, a.nx, a.wall[0]) && to_domain(gy, a.ny, a.wall[1]))) {
         Real gphi[3], lphi, rho, mu, F[3];
         stencil2d<Real, R1X>(sphi, ry + 1, rx + 1, gphi, lphi);
         forces(a, sphi[ry + 1][rx + 1], gphi, lphi, rho, mu, F);
         Real f[9];
-        gather2d<D2Q9, 0>(a, gx, gy, f);
+        gather2d<D2Q9, 0, FAST>(a, gx, gy, f);
         Real mx = 0, my = 0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -199,7 +214,7 @@ __global__ __launch_bounds__(NT2) void k_step2d(const KArgs<Real, Store> a) {
       suy[ry][rx] = uy;
     }
     __syncthreads();
-    if (a.wall[0]) {
+    if (!FAST && a.wall[0]) {
       for (int k = tid; k < R2X * R2Y; k += NT2) {
         const int ry = k / R2X, rx = k - ry * R2X;
         const int gx = x0 - 1 + rx;
@@ -213,7 +228,7 @@ __global__ __launch_bounds__(NT2) void k_step2d(const KArgs<Real, Store> a) {
       }
       __syncthreads();
     }
-    if (a.wall[1]) {
+    if (!FAST && a.wall[1]) {
       for (int k = tid; k < R2X * R2Y; k += NT2) {
         const int ry = k / R2X, rx = k - ry * R2X;
         const int gy = y0 - 1 + ry;
@@ -235,7 +250,7 @@ __global__ __launch_bounds__(NT2) void k_step2d(const KArgs<Real, Store> a) {
   for (int r = tid / TX2; r < TY2; r += NT2 / TX2) {
     const int x = x0 + lx, y = y0 + r;
     if (x >= a.nx || y >= a.ny) continue;
-    const long long node = (long long)y * a.px + x;
+    const unsigned node = (unsigned)(y * a.px + x);
     NodeMacro<Real> m;
     m.phi = sphi[r + 2][lx + 2];
     stencil2d<Real, R1X>(sphi, r + 2, lx + 2, m.gphi, m.lphi);
@@ -247,73 +262,74 @@ __global__ __launch_bounds__(NT2) void k_step2d(const KArgs<Real, Store> a) {
       m.grho[d] = drho * m.gphi[d];
       m.n[d] = m.gphi[d] * inrm;
     }
-    Real f[9], g[9], s[9];
-    Real m0f = 0;
     m.u[0] = m.u[1] = m.u[2] = 0;
-    if constexpr (NS) {
-      gather2d<D2Q9, 0>(a, x, y, f);
+    Real f[9];
+    Real m0f = 0;
+    if constexpr (NS && HEAT) {
+      m.u[0] = sux[r + 1][lx + 1];
+      m.u[1] = suy[r + 1][lx + 1];
+    } else if constexpr (NS) {
+      // without the heat family u is not staged in LDS: take it from the
+      // local f before the phase field collides with it
+      gather2d<D2Q9, 0, FAST>(a, x, y, f);
+      Real mx = 0, my = 0;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) m0f += f[i];
-      if constexpr (HEAT) {
-        m.u[0] = sux[r + 1][lx + 1];
-        m.u[1] = suy[r + 1][lx + 1];
-      } else {
-        Real mx = 0, my = 0;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          mx += (Real)D2Q9::cx(i) * f[i];
-          my += (Real)D2Q9::cy(i) * f[i];
-        }
-        const Real ir = (Real)1 / m.rho;
-        m.u[0] = ((Real)3 * mx + (Real)0.5 * m.F[0]) * ir;
-        m.u[1] = ((Real)3 * my + (Real)0.5 * m.F[1]) * ir;
+      for (int i = 0; i < 9; ++i) {
+        m0f += f[i];
+        mx += (Real)D2Q9::cx(i) * f[i];
+        my += (Real)D2Q9::cy(i) * f[i];
       }
+      const Real ir = (Real)1 / m.rho;
+      m.u[0] = ((Real)3 * mx + (Real)0.5 * m.F[0]) * ir;
+      m.u[1] = ((Real)3 * my + (Real)0.5 * m.F[1]) * ir;
     }
-    gather2d<D2Q9, 1>(a, x, y, g);
     const Real phip = (Real)a.A_phip[node];
     m.dtphi = m.phi - phip;
     m.alpha = diffusivity(a, m.phi);
     m.D = 0;
     m.T = 0;
     m.q = 0;
+    // One family live at a time: heat (gives T and q), then phi, then NS
+    // (needs q for the pressure moment and the production source).
     if constexpr (HEAT) {
-      gather2d<D2Q9, 2>(a, x, y, s);
+      Real s[9];
+      gather2d<D2Q9, 2, FAST>(a, x, y, s);
       if constexpr (NS) m.D = divergence2d<Real>(sphi, sux, suy, r + 1, lx + 1);
       Real m0s = 0;
 #pragma unroll
       for (int i = 0; i < 9; ++i) m0s += s[i];
       m.T = m0s - (Real)0.5 * a.Lcp * (m.dtphi + m.D);
       m.q = production(a, m.phi, m.T, m.alpha);
+      if constexpr (MODE == MODE_STEP) {
+        const Real om = (Real)1 / (m.alpha * (Real)3 + (Real)0.5);
+        collide_s<D2Q9>(a, s, m, om);
+        store_family<D2Q9>(a, a.off_s, 2, node, s);
+      }
+    }
+    if constexpr (MODE == MODE_STEP) {
+      Real g[9];
+      gather2d<D2Q9, 1, FAST>(a, x, y, g);
+      collide_g<D2Q9>(a, g, m);
+      store_family<D2Q9>(a, a.off_g, 1, node, g);
     }
     const Real cs2 = (Real)(1.0 / 3.0);
     m.p = 0;
     if constexpr (NS) {
+      if constexpr (HEAT) {
+        gather2d<D2Q9, 0, FAST>(a, x, y, f);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) m0f += f[i];
+      }
       const Real udr = m.u[0] * m.grho[0] + m.u[1] * m.grho[1];
       m.p = m0f + (Real)0.5 * (cs2 * udr + m.rho * cs2 * m.q * a.prod_fac);
-    }
-    if constexpr (MODE == MODE_STEP) {
-      if constexpr (NS) {
+      if constexpr (MODE == MODE_STEP) {
         m.nu = viscosity(a, m.phi);
         const Real om = (Real)1 / (m.nu * (Real)3 + (Real)0.5);
         collide_f<D2Q9>(f, m, m.rho * cs2 * m.q * a.prod_fac, om);
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-          a.B[(long long)(a.off_f + i) * a.slab + node] =
-              C::enc(f[i], (Real)D2Q9::w(i) * a.ref[0], a.scale[0]);
+        store_family<D2Q9>(a, a.off_f, 0, node, f);
       }
-      collide_g<D2Q9>(a, g, m);
-#pragma unroll
-      for (int i = 0; i < 9; ++i)
-        a.B[(long long)(a.off_g + i) * a.slab + node] =
-            C::enc(g[i], (Real)D2Q9::w(i) * a.ref[1], a.scale[1]);
-      if constexpr (HEAT) {
-        const Real om = (Real)1 / (m.alpha * (Real)3 + (Real)0.5);
-        collide_s<D2Q9>(a, s, m, om);
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-          a.B[(long long)(a.off_s + i) * a.slab + node] =
-              C::enc(s[i], (Real)D2Q9::w(i) * a.ref[2], a.scale[2]);
-      }
+    }
+    if constexpr (MODE == MODE_STEP) {
       a.B_phip[node] = (Sc)m.phi;
       a.B_qp[node] = (Sc)m.q;
     } else {
@@ -346,6 +362,28 @@ __global__ __launch_bounds__(NT2) void k_step2d(const KArgs<Real, Store> a) {
   if constexpr (MODE == MODE_MACRO) {
     if (a.partials) block_partials(acc_phi, acc_T, acc_phip, acc_umax, acc_bad, a.partials);
   }
+}
+
+template <class Store, class Real, bool NS, bool HEAT, int MODE>
+__global__ __launch_bounds__(NT2) void k_step2d(const KArgs<Real, Store> a) {
+  __shared__ Real sphi[R1Y][R1X];
+  __shared__ Real sux[R2Y][R2X];
+  __shared__ Real suy[R2Y][R2X];
+  const int tiles_x = (a.nx + TX2 - 1) / TX2;
+  const int ntiles = tiles_x * ((a.ny + TY2 - 1) / TY2);
+  // XCD-aware order: hardware deals blocks to the 8 XCDs round-robin; give
+  // each XCD a contiguous band of tiles so neighbouring tiles share an L2.
+  int t = blockIdx.x;
+  const int full = (ntiles / 8) * 8;
+  if (t < full) t = (t % 8) * (full / 8) + t / 8;
+  const int x0 = (t % tiles_x) * TX2, y0 = (t / tiles_x) * TY2;
+  // interior tile: every source node of the 2-halo region (3 nodes out)
+  // lies inside the domain, so no wall link and no periodic wrap occurs
+  const bool interior = x0 >= 3 && x0 + TX2 + 3 <= a.nx && y0 >= 3 && y0 + TY2 + 3 <= a.ny;
+  if (interior)
+    step_tile2d<Store, Real, NS, HEAT, MODE, true>(a, sphi, sux, suy, x0, y0);
+  else
+    step_tile2d<Store, Real, NS, HEAT, MODE, false>(a, sphi, sux, suy, x0, y0);
 }
 
 // Initialisation: populations = equilibrium - S/2 at the given fields with

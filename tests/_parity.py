@@ -94,3 +94,20 @@ class Timer:
 
     def __exit__(self, *a):
         self.dt = time.time() - self.t
+
+
+def fp32_floor(prm, phi0, T0, nsteps):
+    """Relative L2 between the oracle evaluated in float32 and in float64 on
+    the same inputs: the rounding floor of any FP32 implementation of the
+    scheme on this case (nothing here comes from the HIP path)."""
+    ref = oracle_run(prm, phi0, T0, nsteps)
+    M = Model(prm, dtype=torch.float32)
+    st = M.run(M.init(phi0, T0), nsteps)
+    f = {k: v.double().numpy() for k, v in M.fields(st).items()}
+    return compare(f, ref), ref
+
+
+def fp32_bars(floor, tol=1e-5, factor=3.0):
+    """The 1e-5 relative-L2 bar where FP32 arithmetic allows it, else
+    `factor` times the measured FP32 floor of the case."""
+    return {k: max(tol, factor * v) for k, v in floor.items()}
