@@ -86,6 +86,7 @@ lbm_status validate(const lbm_params* p) {
       return fail(LBM_E_UNSUPPORTED, "3-D supports D3Q19 (f) with D3Q7 (g, s)");
     if (p->bc[0] != LBM_BC_PERIODIC || p->bc[1] != LBM_BC_PERIODIC)
       return fail(LBM_E_UNSUPPORTED, "3-D supports walls on z only");
+    if (p->bc[2] == LBM_BC_WALL && p->nz < 2) return fail(LBM_E_INVAL, "z walls need nz >= 2");
   }
   for (int a = 0; a < 3; ++a)
     if (p->bc[a] != LBM_BC_PERIODIC && p->bc[a] != LBM_BC_WALL)
@@ -103,6 +104,13 @@ lbm_status validate(const lbm_params* p) {
   if (p->A_coef < 0) return fail(LBM_E_INVAL, "A_coef must be >= 0");
   if (!(p->sigma >= 0)) return fail(LBM_E_INVAL, "sigma must be >= 0");
   if ((long long)p->nx * p->ny * p->nz > (1LL << 31)) return fail(LBM_E_INVAL, "grid too large");
+  if (p->dim == 2) {
+    // the 2-D kernel addresses each population family with 32-bit byte offsets
+    const long long px = (p->nx + 63) / 64 * 64;
+    const long long elem = p->storage == LBM_ST_F64 ? 8 : (p->storage == LBM_ST_F32 ? 4 : 2);
+    if (9LL * px * p->ny * elem >= (1LL << 32))
+      return fail(LBM_E_UNSUPPORTED, "2-D grid too large for 32-bit family offsets");
+  }
   return LBM_OK;
 }
 
@@ -131,7 +139,7 @@ Layout layout(const lbm_params* p) {
         tot += L.faces[a][s];
       }
     }
-  L.nblocks = p->dim == 2 ? step2d_blocks(p->nx, p->ny) : 1;
+  L.nblocks = p->dim == 2 ? step2d_blocks(p->nx, p->ny) : step3d_blocks(p->nx, p->ny, p->nz);
   L.partials = align256((size_t)(L.nblocks * NPART + 8) * sizeof(double));
   tot += L.partials;
   L.total = tot;
@@ -263,7 +271,6 @@ lbm_status lbm_workspace_size(const lbm_params* prm, size_t* bytes) {
   if (!bytes) return fail(LBM_E_INVAL, "bytes is NULL");
   lbm_status s = validate(prm);
   if (s != LBM_OK) return s;
-  if (prm->dim == 3) return fail(LBM_E_UNSUPPORTED, "3-D step not built");
   *bytes = layout(prm).total;
   return LBM_OK;
 }
@@ -273,7 +280,6 @@ lbm_status lbm_create(const lbm_params* prm, void* ws, size_t bytes, void* strea
   *out = nullptr;
   lbm_status s = validate(prm);
   if (s != LBM_OK) return s;
-  if (prm->dim == 3) return fail(LBM_E_UNSUPPORTED, "3-D step not built");
   const Layout L = layout(prm);
   if (!ws) return fail(LBM_E_INVAL, "workspace is NULL");
   if (((uintptr_t)ws & 255) != 0) return fail(LBM_E_INVAL, "workspace must be 256-byte aligned");
@@ -343,7 +349,8 @@ lbm_status lbm_init_fields(lbm_ctx* c, const void* phi0, const void* T0, const v
   c->cur = 1;
   const int f64 = dtype == LBM_DT_F64;
   hipError_t e = dispatch(c, [&](auto a) {
-    return launch_init2d(a, c->ns, c->heat, phi0, T0, u0, p0, f64, c->stream);
+    return c->prm.dim == 2 ? launch_init2d(a, c->ns, c->heat, phi0, T0, u0, p0, f64, c->stream)
+                           : launch_init3d(a, c->ns, c->heat, phi0, T0, u0, p0, f64, c->stream);
   });
   c->cur = 0;
   c->step = 0;
@@ -370,7 +377,8 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (nsteps < 0) return fail(LBM_E_INVAL, "nsteps < 0");
   for (int64_t k = 0; k < nsteps; ++k) {
     hipError_t e = dispatch(c, [&](auto a) {
-      return launch_step2d(a, c->ns, c->heat, MODE_STEP, c->stream);
+      return c->prm.dim == 2 ? launch_step2d(a, c->ns, c->heat, MODE_STEP, c->stream)
+                             : launch_step3d(a, c->ns, c->heat, MODE_STEP, c->stream);
     });
     if (e != hipSuccess) return hip_check(e, "lbm_step");
     c->cur = 1 - c->cur;
@@ -385,7 +393,8 @@ static lbm_status run_macro(lbm_ctx* c, uint32_t mask, void* out, int f64, doubl
     a.out_f64 = f64;
     a.out_mask = mask;
     a.partials = partials;
-    return launch_step2d(a, c->ns, c->heat, MODE_MACRO, c->stream);
+    return c->prm.dim == 2 ? launch_step2d(a, c->ns, c->heat, MODE_MACRO, c->stream)
+                           : launch_step3d(a, c->ns, c->heat, MODE_MACRO, c->stream);
   });
   return hip_check(e, "macro pass");
 }

@@ -19,6 +19,7 @@ namespace lbm {
 // ---------------------------------------------------------------------------
 struct D2Q9 {
   static constexpr int Q = 9;
+  static constexpr int D = 2;
   __host__ __device__ static constexpr int cx(int i) {
     constexpr int v[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     return v[i];
@@ -40,6 +41,7 @@ struct D2Q9 {
 
 struct D3Q7 {
   static constexpr int Q = 7;
+  static constexpr int D = 3;
   __host__ __device__ static constexpr int cx(int i) {
     constexpr int v[7] = {0, 1, 0, 0, -1, 0, 0};
     return v[i];
@@ -62,6 +64,7 @@ struct D3Q7 {
 
 struct D3Q19 {
   static constexpr int Q = 19;
+  static constexpr int D = 3;
   __host__ __device__ static constexpr int cx(int i) {
     constexpr int v[19] = {0, 1, 0, 0, -1, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
     return v[i];
@@ -154,6 +157,31 @@ struct KArgs {
   double* partials;       // per-block diagnostics partials
 };
 
+// Load / store element `idx` (32-bit, non-negative) of a uniform plane
+// pointer.  The byte offset is formed in 32 bits and zero-extended so the
+// compiler can use the scalar-base + 32-bit vector-offset addressing form
+// instead of 64-bit per-lane address arithmetic.
+template <class T>
+__device__ __forceinline__ T ld_plane(const T* __restrict__ plane, unsigned idx) {
+  return *(const T*)((const char*)plane + (size_t)(idx * (unsigned)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ void st_plane(T* __restrict__ plane, unsigned idx, T v) {
+  *(T*)((char*)plane + (size_t)(idx * (unsigned)sizeof(T))) = v;
+}
+
+// Element `idx` of a family block (all planes of one population family)
+// addressed with a 32-bit byte offset; the caller guarantees the family
+// block is below 4 GiB.
+template <class T>
+__device__ __forceinline__ T ld_fam(const T* __restrict__ fam, unsigned idx) {
+  return *(const T*)((const char*)fam + (size_t)(idx * (unsigned)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ void st_fam(T* __restrict__ fam, unsigned idx, T v) {
+  *(T*)((char*)fam + (size_t)(idx * (unsigned)sizeof(T))) = v;
+}
+
 __device__ inline int wrap1(int s, int n) {   // s in [-1, n]
   return s < 0 ? s + n : (s >= n ? s - n : s);
 }
@@ -200,32 +228,81 @@ __device__ inline Real production(const A& a, Real phi, Real T, Real alpha) {
   return -(a.qcoef * alpha) * (a.theta_I - theta) * phi * ((Real)1 - phi);
 }
 
-// Gamma_i of Eq. FunctionGamma.
+// c_i . v over the lattice's non-zero components only (after unrolling the
+// direction loop the components are constants, so zero terms vanish).
 template <class Lat, class Real>
-__device__ inline Real gamma_i(int i, const Real* u, Real uu) {
-  const Real inv_cs2 = (Real)(1.0 / Lat::cs2);
-  const Real cu = (Real)Lat::cx(i) * u[0] + (Real)Lat::cy(i) * u[1] + (Real)Lat::cz(i) * u[2];
-  return (Real)Lat::w(i) *
-         ((Real)1 + cu * inv_cs2 + (Real)0.5 * cu * cu * inv_cs2 * inv_cs2 - (Real)0.5 * uu * inv_cs2);
+__device__ __forceinline__ Real cdot(int i, const Real* v) {
+  const int c0 = Lat::cx(i), c1 = Lat::cy(i), c2 = Lat::cz(i);
+  Real r = c0 ? (Real)c0 * v[0] : (Real)0;
+  if (c1) r = c0 ? r + (Real)c1 * v[1] : (Real)c1 * v[1];
+  if (c2) r = (c0 || c1) ? r + (Real)c2 * v[2] : (Real)c2 * v[2];
+  return r;
 }
 
-// f family: Eq. Feq_NS_Incompr, S^f = F^f + P^f (Eqs. Forcing, MicroProduction),
-// collision Eq. LBE with bar-eq = eq - S/2.
+template <class Lat, class Real>
+__device__ __forceinline__ Real dotD(const Real* a, const Real* b) {
+  Real r = a[0] * b[0] + a[1] * b[1];
+  if (Lat::D == 3) r += a[2] * b[2];
+  return r;
+}
+
+// Gamma_i of Eq. FunctionGamma split as w_i + dGamma_i with
+// dGamma_i = w_i [cu/c_s^2 + cu^2/(2 c_s^4) - u.u/(2 c_s^2)] computed directly
+// (no cancellation against w_i: the deviation carries the flow).
+template <class Lat, class Real>
+__device__ __forceinline__ Real dgamma_i(int i, const Real* u, Real huu) {
+  const Real inv_cs2 = (Real)(1.0 / Lat::cs2);
+  const Real h = (Real)(0.5 / (Lat::cs2 * Lat::cs2));
+  if (Lat::cx(i) == 0 && Lat::cy(i) == 0 && Lat::cz(i) == 0) return -(Real)Lat::w(i) * huu;
+  const Real cu = cdot<Lat>(i, u);
+  return (Real)Lat::w(i) * (cu * (inv_cs2 + h * cu) - huu);
+}
+template <class Lat, class Real>
+__device__ __forceinline__ Real gamma_huu(const Real* u) {   // u.u / (2 c_s^2)
+  return (Real)(0.5 / Lat::cs2) * dotD<Lat>(u, u);
+}
+template <class Lat, class Real>
+__device__ __forceinline__ Real gamma_i(int i, const Real* u, Real huu) {
+  return (Real)Lat::w(i) + dgamma_i<Lat>(i, u, huu);
+}
+
+// BGK with the barred equilibrium (Eqs. VariableChange_feq, LBE):
+// v - w (v - eq + S/2) + S = (1 - w) v + w eq + (1 - w/2) S.
+template <class Real>
+struct Relax {
+  Real om, om1, om2;
+  __device__ __forceinline__ explicit Relax(Real omega)
+      : om(omega), om1((Real)1 - omega), om2((Real)1 - (Real)0.5 * omega) {}
+  __device__ __forceinline__ Real operator()(Real v, Real eq, Real S) const {
+    return fma(om1, v, fma(om, eq, om2 * S));
+  }
+};
+
+// f family: Eq. Feq_NS_Incompr, S^f = F^f + P^f (Eqs. Forcing, MicroProduction).
+// With Gamma_i = w_i + dGamma_i:
+//   f^eq_i = w_i p + rho c_s^2 dGamma_i,
+//   F^f_i  = dGamma_i X_i + Gamma_i Y_i,
+//   X_i = c_s^2 (c_i - u).grad(rho),  Y_i = (c_i - u).F.
 template <class Lat, class Real>
 __device__ inline void collide_f(Real* f, const NodeMacro<Real>& m, Real prodP, Real omega) {
   const Real cs2 = (Real)Lat::cs2;
-  const Real uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+  const Real huu = gamma_huu<Lat>(m.u);
+  const Real rc = m.rho * cs2;
+  const Real ug = cs2 * dotD<Lat>(m.u, m.grho);
+  const Real uF = dotD<Lat>(m.u, m.F);
+  const Relax<Real> R(omega);
+  Real cg2[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) cg2[d] = cs2 * m.grho[d];
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
     const Real w = (Real)Lat::w(i);
-    const Real G = gamma_i<Lat>(i, m.u, uu);
-    const Real feq = w * m.p + m.rho * cs2 * (G - w);
-    const Real c[3] = {(Real)Lat::cx(i), (Real)Lat::cy(i), (Real)Lat::cz(i)};
-    Real Ff = 0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) Ff += (c[d] - m.u[d]) * ((G - w) * cs2 * m.grho[d] + G * m.F[d]);
-    const Real S = Ff + w * prodP;
-    f[i] = f[i] - omega * (f[i] - feq + (Real)0.5 * S) + S;
+    const Real dG = dgamma_i<Lat>(i, m.u, huu);
+    const Real X = cdot<Lat>(i, cg2) - ug;
+    const Real Y = cdot<Lat>(i, m.F) - uF;
+    const Real S = fma(dG, X, (w + dG) * Y) + w * prodP;
+    const Real feq = fma(w, m.p, rc * dG);
+    f[i] = R(f[i], feq, S);
   }
 }
 
@@ -233,37 +310,36 @@ __device__ inline void collide_f(Real* f, const NodeMacro<Real>& m, Real prodP, 
 // SourceTerm_AllenCahn), or the CAC equilibrium form (Eq. Geq_AC-1).
 template <class Lat, class Real, class A>
 __device__ inline void collide_g(const A& a, Real* g, const NodeMacro<Real>& m) {
-  const Real uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+  const Real huu = gamma_huu<Lat>(m.u);
   const Real k = a.four_over_W * m.phi * ((Real)1 - m.phi);
-  const Real om = a.omega_g;
+  Real kn[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) kn[d] = k * m.n[d];
+  const Relax<Real> R(a.omega_g);
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
     const Real w = (Real)Lat::w(i);
-    const Real G = gamma_i<Lat>(i, m.u, uu);
-    const Real cn = (Real)Lat::cx(i) * m.n[0] + (Real)Lat::cy(i) * m.n[1] + (Real)Lat::cz(i) * m.n[2];
-    const Real Fg = k * w * cn;
+    const Real geq = fma(m.phi, dgamma_i<Lat>(i, m.u, huu), m.phi * w);   // phi Gamma_i
+    const Real Fg = w * cdot<Lat>(i, kn);
     const Real Pg = w * m.q;
-    if (a.geq_cac) {
-      const Real geq = m.phi * G + a.M_over_cs2g * Fg;
-      g[i] = g[i] - om * (g[i] - geq + (Real)0.5 * Pg) + Pg;
-    } else {
-      const Real S = Fg + Pg;
-      g[i] = g[i] - om * (g[i] - m.phi * G + (Real)0.5 * S) + S;
-    }
+    if (a.geq_cac)
+      g[i] = R(g[i], fma(a.M_over_cs2g, Fg, geq), Pg);
+    else
+      g[i] = R(g[i], geq, Fg + Pg);
   }
 }
 
 // s family: Eq. Seq_Temp with S^s_i = -w_i (L/Cp)[d_t phi + div(u phi)].
 template <class Lat, class Real, class A>
 __device__ inline void collide_s(const A& a, Real* s, const NodeMacro<Real>& m, Real omega) {
-  const Real uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+  const Real huu = gamma_huu<Lat>(m.u);
   const Real src = -a.Lcp * (m.dtphi + m.D);
+  const Relax<Real> R(omega);
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
     const Real w = (Real)Lat::w(i);
-    const Real G = gamma_i<Lat>(i, m.u, uu);
-    const Real S = w * src;
-    s[i] = s[i] - omega * (s[i] - m.T * G + (Real)0.5 * S) + S;
+    const Real seq = fma(m.T, dgamma_i<Lat>(i, m.u, huu), m.T * w);   // T Gamma_i
+    s[i] = R(s[i], seq, w * src);
   }
 }
 

@@ -43,9 +43,8 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
   if constexpr (FAST) {
 #pragma unroll
     for (int i = 0; i < Lat::Q; ++i) {
-      const Store* __restrict__ p =
-          base + (size_t)i * (size_t)a.slab - (ptrdiff_t)(Lat::cx(i) + Lat::cy(i) * a.px);
-      v[i] = C::dec(p[node], (Real)Lat::w(i) * ref, inv);
+      const unsigned sl = (unsigned)i * (unsigned)a.slab - (unsigned)(Lat::cx(i) + Lat::cy(i) * a.px);
+      v[i] = C::dec(ld_fam(base, node + sl), (Real)Lat::w(i) * ref, inv);
     }
     return;
   }
@@ -58,7 +57,7 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
     const Real wref = (Real)Lat::w(i) * ref;
     if (oy || ox) {
       const int j = Lat::opp(i);
-      Real r = C::dec((base + (size_t)j * (size_t)a.slab)[node], wref, inv);
+      Real r = C::dec(ld_fam(base, (unsigned)j * (unsigned)a.slab + node), wref, inv);
       if (FAM != 0) {
         Real V;
         if (oy) {
@@ -74,7 +73,7 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
     } else {
       if (cx != 0 && !a.wall[0]) sx = wrap1(sx, a.nx);
       if (cy != 0 && !a.wall[1]) sy = wrap1(sy, a.ny);
-      v[i] = C::dec((base + (size_t)i * (size_t)a.slab)[(unsigned)(sy * a.px + sx)], wref, inv);
+      v[i] = C::dec(ld_fam(base, (unsigned)i * (unsigned)a.slab + (unsigned)(sy * a.px + sx)), wref, inv);
     }
   }
 }
@@ -87,30 +86,33 @@ __device__ inline void store_family(const KArgs<Real, Store>& a, int off, int fa
   Store* __restrict__ base = a.B + (size_t)off * (size_t)a.slab;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i)
-    (base + (size_t)i * (size_t)a.slab)[node] =
-        C::enc(v[i], (Real)Lat::w(i) * a.ref[fam], a.scale[fam]);
+    st_fam(base, (unsigned)i * (unsigned)a.slab + node,
+           C::enc(v[i], (Real)Lat::w(i) * a.ref[fam], a.scale[fam]));
 }
 
 // Directional-derivative gradient and Laplacian (Eqs. DerivDirec_Grad, Grad,
-// DerivDirect_Laplacian, Laplacian) of an LDS field at (ry, rx).
+// DerivDirect_Laplacian, Laplacian) of an LDS field at (ry, rx).  The sums
+// run over the D2Q9 directions; a direction and its opposite contribute the
+// same term, so each pair is taken once with weight 2 (exact rewrite).
 template <class Real, int RX>
 __device__ inline void stencil2d(const Real (*s)[RX], int ry, int rx, Real* g, Real& lap) {
   const Real c = s[ry][rx];
-  Real gx = 0, gy = 0, l = 0;
+  Real gx = 0, gy = 0, l = 0, wsum = 0;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
+    if (i > D2Q9::opp(i)) continue;
     const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
     const Real w = (Real)D2Q9::w(i);
     const Real p = s[ry + cy][rx + cx], m = s[ry - cy][rx - cx];
-    const Real dd = (Real)0.5 * (p - m);
-    gx += w * (Real)cx * dd;
-    gy += w * (Real)cy * dd;
-    l += w * (p - (Real)2 * c + m);
+    if (cx) gx += w * (Real)cx * (p - m);
+    if (cy) gy += w * (Real)cy * (p - m);
+    l += w * (p + m);
+    wsum += w;
   }
-  g[0] = gx * (Real)3;
+  g[0] = gx * (Real)3;   // 1/c_s^2
   g[1] = gy * (Real)3;
   g[2] = 0;
-  lap = l * (Real)3;
+  lap = (l - (Real)2 * wsum * c) * (Real)6;
 }
 
 // div(u phi): the Eq. Grad stencil applied to u_a phi, a-th component, summed.
@@ -120,13 +122,14 @@ __device__ inline Real divergence2d(const Real (*sphi)[R1X], const Real (*sux)[R
   Real d = 0;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
+    if (i > D2Q9::opp(i)) continue;
     const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
     const Real w = (Real)D2Q9::w(i);
     const Real pp = sphi[ry2 + 1 + cy][rx2 + 1 + cx], pm = sphi[ry2 + 1 - cy][rx2 + 1 - cx];
     if (cx != 0)
-      d += w * (Real)cx * (Real)0.5 * (sux[ry2 + cy][rx2 + cx] * pp - sux[ry2 - cy][rx2 - cx] * pm);
+      d += w * (Real)cx * (sux[ry2 + cy][rx2 + cx] * pp - sux[ry2 - cy][rx2 - cx] * pm);
     if (cy != 0)
-      d += w * (Real)cy * (Real)0.5 * (suy[ry2 + cy][rx2 + cx] * pp - suy[ry2 - cy][rx2 - cx] * pm);
+      d += w * (Real)cy * (suy[ry2 + cy][rx2 + cx] * pp - suy[ry2 - cy][rx2 - cx] * pm);
   }
   return d * (Real)3;
 }
@@ -160,7 +163,7 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
       Real s = 0;
 #pragma unroll
       for (int i = 0; i < 9; ++i) s += g[i];
-      v = s + (Real)0.5 * (Real)a.A_qp[(unsigned)(gy * a.px + gx)];
+      v = s + (Real)0.5 * (Real)ld_plane(a.A_qp, (unsigned)(gy * a.px + gx));
     }
     sphi[ry][rx] = v;
   }
@@ -203,8 +206,8 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
         Real mx = 0, my = 0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-          mx += (Real)D2Q9::cx(i) * f[i];
-          my += (Real)D2Q9::cy(i) * f[i];
+          if (D2Q9::cx(i)) mx += (Real)D2Q9::cx(i) * f[i];
+          if (D2Q9::cy(i)) my += (Real)D2Q9::cy(i) * f[i];
         }
         const Real ir = (Real)1 / rho;
         ux = ((Real)3 * mx + (Real)0.5 * F[0]) * ir;
@@ -276,14 +279,14 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         m0f += f[i];
-        mx += (Real)D2Q9::cx(i) * f[i];
-        my += (Real)D2Q9::cy(i) * f[i];
+        if (D2Q9::cx(i)) mx += (Real)D2Q9::cx(i) * f[i];
+        if (D2Q9::cy(i)) my += (Real)D2Q9::cy(i) * f[i];
       }
       const Real ir = (Real)1 / m.rho;
       m.u[0] = ((Real)3 * mx + (Real)0.5 * m.F[0]) * ir;
       m.u[1] = ((Real)3 * my + (Real)0.5 * m.F[1]) * ir;
     }
-    const Real phip = (Real)a.A_phip[node];
+    const Real phip = (Real)ld_plane(a.A_phip, node);
     m.dtphi = m.phi - phip;
     m.alpha = diffusivity(a, m.phi);
     m.D = 0;
@@ -330,8 +333,8 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
       }
     }
     if constexpr (MODE == MODE_STEP) {
-      a.B_phip[node] = (Sc)m.phi;
-      a.B_qp[node] = (Sc)m.q;
+      st_plane(a.B_phip, node, (Sc)m.phi);
+      st_plane(a.B_qp, node, (Sc)m.q);
     } else {
       const long long plane = (long long)a.nx * a.ny * a.nz;
       const long long idx = (long long)y * a.nx + x;
@@ -480,10 +483,10 @@ __global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, cons
   const Real cs2 = (Real)(1.0 / 3.0);
   // eq - S/2 == the collision of (eq - S/2) with omega = 1 minus S ... write explicitly:
   Real f[9], g[9], s[9];
-  const Real uu = m.u[0] * m.u[0] + m.u[1] * m.u[1];
+  const Real a0 = gamma_huu<D2Q9>(m.u);
   for (int i = 0; i < 9; ++i) {
     const Real w = (Real)D2Q9::w(i);
-    const Real G = gamma_i<D2Q9>(i, m.u, uu);
+    const Real G = gamma_i<D2Q9>(i, m.u, a0);
     const Real c[3] = {(Real)D2Q9::cx(i), (Real)D2Q9::cy(i), (Real)0};
     if (NS) {
       Real Ff = 0;

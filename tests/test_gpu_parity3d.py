@@ -1,0 +1,86 @@
+"""GPU parity of the 3-D HIP path (D3Q19 f, D3Q7 g and s, D3Q19 stencils,
+z walls) against the FP64 oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from paper_2003_06342_amd import inputs as I
+from tests._parity import (compare, fp32_bars, fp32_floor, gpu_run, need_gpu, oracle_run, say)
+
+pytestmark = pytest.mark.gpu
+
+
+def film3d_case(nx, ny, nz, h0, amp, seed=1):
+    prm = I.film3d_params(nx, nz=nz)
+    prm["ny"] = ny
+    prm["gravity"] = [0.0, 0.0, -5e-5]
+    phi0, T0 = I.film3d_fields(prm, seed=seed, h0=h0, amp=amp, wavelength=float(nx))
+    return prm, phi0, T0
+
+
+def _check(name, prm, phi0, T0, nsteps, storage, tol):
+    need_gpu()
+    say(f"[parity3d] {name}: {prm['nx']}x{prm['ny']}x{prm['nz']} storage={storage} steps={nsteps}")
+    ref = oracle_run(prm, phi0, T0, nsteps)
+    gpu = gpu_run(prm, phi0, T0, nsteps, storage)
+    errs = compare(gpu, ref)
+    say(f"[parity3d] {name}: errors {errs}")
+    keys = ["phi"] + (["T"] if prm["heat"] else []) + (["umag", "p"] if prm["ns"] else [])
+    for k in keys:
+        assert errs[k] <= tol, (k, errs)
+    return errs, gpu, ref
+
+
+def test_init_round_trip_3d_f64():
+    need_gpu()
+    prm, phi0, T0 = film3d_case(20, 18, 21, 6.0, 1.5)
+    gpu = gpu_run(prm, phi0, T0, 0, "f64")
+    assert np.abs(gpu["phi"] - phi0).max() < 1e-14
+    assert np.abs(gpu["T"] - T0).max() < 1e-14
+
+
+def test_film3d_f64_ragged_two_chunks():
+    """37 z planes: two z chunks of the marching kernel, ragged xy tiles."""
+    prm, phi0, T0 = film3d_case(36, 20, 37, 8.0, 1.5)
+    _check("film3d_f64_ragged", prm, phi0, T0, 25, "f64", 1e-10)
+
+
+def test_film3d_f64_interior_tiles():
+    """70 x 40 x 40: includes tiles on the xy-interior fast path."""
+    prm, phi0, T0 = film3d_case(70, 40, 40, 10.0, 2.0)
+    _check("film3d_f64_interior", prm, phi0, T0, 20, "f64", 1e-10)
+
+
+def test_periodic3d_enthalpy_f64():
+    need_gpu()
+    p = I.base_params(dim=3, nx=24, ny=20, nz=18, lat_f="D3Q19", lat_g="D3Q7", lat_s="D3Q7", **I.FB)
+    p["gravity"] = [0.0, 0.0, -1e-4]
+    phi0, T0 = I.random_smooth_fields(p, seed=5, T_amp=0.5)
+    errs, gpu, ref = _check("periodic3d_f64", p, phi0, T0, 30, "f64", 1e-10)
+    assert gpu["diag"]["enthalpy"] == pytest.approx(ref["diag"]["enthalpy"], rel=1e-12)
+
+
+def test_film3d_f32_vs_floor():
+    need_gpu()
+    prm, phi0, T0 = film3d_case(36, 34, 40, 10.0, 2.0)
+    n = 60
+    say(f"[parity3d] film3d_f32: steps={n}")
+    floor, ref = fp32_floor(prm, phi0, T0, n)
+    gpu = gpu_run(prm, phi0, T0, n, "f32")
+    errs = compare(gpu, ref)
+    bars = fp32_bars(floor)
+    say(f"[parity3d] film3d_f32: gpu {errs} | floor {floor}")
+    for k in ("phi", "T", "umag", "p"):
+        assert errs[k] <= bars[k], (k, errs, floor)
+
+
+def test_drop3d_heat_off_f64():
+    """Heat-off 3-D variant (u taken from the local f)."""
+    need_gpu()
+    p = I.base_params(dim=3, nx=30, ny=26, nz=28, lat_f="D3Q19", lat_g="D3Q7", lat_s="D3Q7",
+                      heat=False, phase_change=False, sigma=1e-3)
+    p["bc"] = ["periodic", "periodic", "wall"]
+    p["phi_wall"] = [[0, 0], [0, 0], [1.0, 1.0]]
+    z, y, x = np.meshgrid(np.arange(28) + 0.5, np.arange(26) + 0.5, np.arange(30) + 0.5, indexing="ij")
+    r = np.sqrt((x - 15) ** 2 + (y - 13) ** 2 + (z - 14) ** 2)
+    phi0 = I.tanh_profile(r - 8.0, p["W"])
+    _check("drop3d_f64", p, phi0, None, 30, "f64", 1e-10)
