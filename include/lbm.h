@@ -164,6 +164,37 @@ lbm_status lbm_get_step(const lbm_ctx* ctx, int64_t* out);
 /* Wait for all work queued on the context's stream; reports HIP errors. */
 lbm_status lbm_sync(lbm_ctx* ctx);
 
+/* ---- Adjoint (2-D, FP32 or FP64 storage, LBM_NS | LBM_HEAT, at most one
+ * walled axis).  Gradients of a loss L(phi^N) of the final phase field with
+ * respect to the initial phase field phi0, the initial temperature T0 and a
+ * wall-temperature row, by a hand-written reverse sweep of the fused step
+ * (transposed node Jacobian, transposed stencils, transposed pull gather;
+ * the anti-bounce-back links of Sec. 3.3 carry T_w linearly).  Memory uses
+ * sqrt(T) checkpointing: snapshots every ceil(sqrt(N)) steps and a
+ * recomputed segment during the reverse sweep. */
+
+/* Bytes of the tape for nsteps (snapshots plus one segment of states). */
+lbm_status lbm_tape_size(const lbm_ctx* ctx, int64_t nsteps, size_t* bytes);
+
+/* Advance nsteps from the current state (normally right after
+ * lbm_init_fields) while recording the tape in dev_tape (caller-owned,
+ * 256-byte aligned, >= lbm_tape_size bytes; borrowed until the next
+ * lbm_forward_taped).  Asynchronous. */
+lbm_status lbm_forward_taped(lbm_ctx* ctx, int64_t nsteps, void* dev_tape, size_t bytes);
+
+/* Bytes of the scratch workspace lbm_backward needs. */
+lbm_status lbm_adjoint_workspace_size(const lbm_ctx* ctx, size_t* bytes);
+
+/* Reverse sweep over the taped steps.  dev_gphi: dL/dphi^N, device array
+ * [ny][nx] of gphi_dtype.  Writes (each nullable) d_phi0 [ny][nx], d_T0
+ * [ny][nx] and the gradient of the wall-temperature face (tw_axis, tw_side)
+ * (nx values for a y wall) as out_dtype.  The context's current state is
+ * left at step N.  Returns LBM_E_STATE if the context stepped after the
+ * tape was recorded.  Asynchronous. */
+lbm_status lbm_backward(lbm_ctx* ctx, const void* dev_gphi, int32_t gphi_dtype, void* dev_ws,
+                        size_t ws_bytes, void* d_phi0, void* d_T0, void* d_Twall,
+                        int32_t tw_axis, int32_t tw_side, int32_t out_dtype);
+
 void lbm_destroy(lbm_ctx* ctx);
 
 /* Message of the last error on the calling thread (never NULL). */

@@ -1,0 +1,32 @@
+"""torch.autograd bridge of the HIP forward step and its hand-written adjoint.
+
+``LBMRun.apply(phi0, Tw, prm, T0, nsteps, storage)`` runs the 2-D film step
+nsteps times from (phi0, T0) with the wall-temperature row Tw on the
+heated floor (face y = 0) and returns phi^N; its backward calls the
+library's reverse sweep (sqrt(T) checkpointing) and returns dL/dphi0 and
+dL/dTw.  Every operation runs in liblbm.so; torch only holds the tensors.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import lbm
+
+
+class LBMRun(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, phi0, Tw, prm, T0, nsteps: int, storage: str = "f32"):
+        sim = lbm.Sim(prm, storage, device=str(phi0.device))
+        sim.set_wall_T(1, 0, Tw.detach())
+        sim.init(phi0.detach(), T0)
+        sim.forward_taped(int(nsteps))
+        phiN = sim.fields(("phi",))["phi"][0].clone()
+        ctx.sim = sim
+        return phiN.to(phi0.dtype)
+
+    @staticmethod
+    def backward(ctx, gphi):
+        g = ctx.sim.backward(gphi.detach().to(torch.float64), tw_face=(1, 0))
+        ctx.sim.close()
+        dphi0 = g["phi0"].reshape(1, *g["phi0"].shape)
+        return dphi0, g["Tw"], None, None, None, None

@@ -5,6 +5,7 @@
 // deterministic FP64 diagnostics reduction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -14,6 +15,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_kernels.h"
+#include "lbm_adjargs.h"
 
 using namespace lbm;
 
@@ -67,6 +69,11 @@ struct lbm_ctx {
   int initialized;
   hipStream_t stream;
   double ref[3], scale[3];
+  // sqrt(T) tape of the last lbm_forward_taped call
+  char* tape;
+  size_t tape_bytes;
+  int64_t tape_n, tape_k, tape_nsnap, tape_end_step;
+  int tape_ready;
 };
 
 namespace {
@@ -204,6 +211,21 @@ KArgs<Real, Store> make_args(const lbm_ctx* c) {
   a.A_qp = (const typename KArgs<Real, Store>::Sc*)c->qp[cur];
   a.B_phip = (typename KArgs<Real, Store>::Sc*)c->phip[1 - cur];
   a.B_qp = (typename KArgs<Real, Store>::Sc*)c->qp[1 - cur];
+  return a;
+}
+
+// Kernel arguments reading state blob `in` and writing state blob `out`
+// (blob layout: populations | phi_prev | q_prev, each 256-byte aligned).
+template <class Real, class Store>
+KArgs<Real, Store> make_args_blobs(const lbm_ctx* c, const char* in, char* out) {
+  KArgs<Real, Store> a = make_args<Real, Store>(c);
+  using Sc = typename KArgs<Real, Store>::Sc;
+  a.A = (const Store*)in;
+  a.A_phip = (const Sc*)(in + c->L.pops);
+  a.A_qp = (const Sc*)(in + c->L.pops + c->L.scal);
+  a.B = (Store*)out;
+  a.B_phip = (Sc*)(out ? out + c->L.pops : nullptr);
+  a.B_qp = (Sc*)(out ? out + c->L.pops + c->L.scal : nullptr);
   return a;
 }
 
@@ -483,5 +505,225 @@ void lbm_destroy(lbm_ctx* c) { delete c; }
 const char* lbm_last_error(void) { return g_err.c_str(); }
 
 const char* lbm_version(void) { return "lbm-phasechange-gfx950 0.1"; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Adjoint: sqrt(T) tape and the reverse sweep (2-D, FP32 / FP64 storage)
+// ===========================================================================
+namespace {
+
+size_t state_bytes(const lbm_ctx* c) { return c->L.pops + 2 * c->L.scal; }
+
+lbm_status adjoint_supported(const lbm_ctx* c) {
+  const lbm_params& p = c->prm;
+  if (p.dim != 2) return fail(LBM_E_UNSUPPORTED, "adjoint is built for 2-D only");
+  if (p.storage != LBM_ST_F32 && p.storage != LBM_ST_F64)
+    return fail(LBM_E_UNSUPPORTED, "adjoint needs FP32 or FP64 storage");
+  if (!c->ns || !c->heat) return fail(LBM_E_UNSUPPORTED, "adjoint needs LBM_NS | LBM_HEAT");
+  if (p.bc[0] == LBM_BC_WALL && p.bc[1] == LBM_BC_WALL)
+    return fail(LBM_E_UNSUPPORTED, "adjoint supports at most one walled axis");
+  return LBM_OK;
+}
+
+void tape_shape(int64_t n, int64_t& k, int64_t& nsnap) {
+  k = 1;
+  while (k * k < n) ++k;
+  nsnap = (n + k - 1) / k;
+}
+
+template <class Real>
+NodeConst<Real> node_const(const lbm_ctx* c) {
+  const KArgs<Real, Real> a = make_args<Real, Real>(c);
+  NodeConst<Real> nc{};
+  nc.rho_l = a.rho_l; nc.rho_g = a.rho_g; nc.K = a.K; nc.H = a.H;
+  nc.four_over_W = a.four_over_W; nc.eps2 = a.eps2;
+  for (int d = 0; d < 2; ++d) { nc.grav[d] = a.grav[d]; nc.body[d] = a.body[d]; }
+  nc.nu_l = a.nu_l; nc.nu_g = a.nu_g; nc.alpha_l = a.alpha_l; nc.alpha_g = a.alpha_g;
+  nc.Lcp = a.Lcp; nc.T_sat = a.T_sat; nc.theta_I = a.theta_I; nc.qcoef = a.qcoef;
+  nc.prod_fac = a.prod_fac; nc.omega_g = a.omega_g; nc.M_over_cs2g = a.M_over_cs2g;
+  nc.visc_linear = a.visc_linear; nc.geq_cac = a.geq_cac; nc.phase_change = a.phase_change;
+  return nc;
+}
+
+size_t adj_ws_bytes(const lbm_ctx* c) {
+  const size_t R = c->prm.storage == LBM_ST_F64 ? 8 : 4;
+  const size_t plane = align256((size_t)c->L.slab * R);
+  const size_t field = align256((size_t)c->prm.nx * c->prm.ny * R);
+  size_t tot = (27 + 2 + 27 + LL_N + 3) * plane + 3 * field;
+  for (int a = 0; a < 2; ++a)
+    if (c->prm.bc[a] == LBM_BC_WALL) tot += 2 * align256((size_t)(a == 0 ? c->prm.ny : c->prm.nx) * R);
+  return tot;
+}
+
+template <class Real>
+lbm_status backward_t(lbm_ctx* c, const void* gphi, int32_t gdt, void* ws, void* d_phi0, void* d_T0,
+                      void* d_Tw, int32_t tw_axis, int32_t tw_side, int32_t odt) {
+  const size_t R = sizeof(Real);
+  const long long nxy = (long long)c->prm.nx * c->prm.ny;
+  const size_t plane = align256((size_t)c->L.slab * R);
+  const size_t field = align256((size_t)nxy * R);
+  char* p = (char*)ws;
+  AdjArgs<Real> b{};
+  b.lA = (Real*)p;       p += 27 * plane;
+  b.lphip = (Real*)p;    p += plane;
+  b.lqp = (Real*)p;      p += plane;
+  b.lP = (Real*)p;       p += 27 * plane;
+  b.lloc = (Real*)p;     p += LL_N * plane;
+  b.fphi = (Real*)p;     p += plane;
+  b.fux = (Real*)p;      p += plane;
+  b.fuy = (Real*)p;      p += plane;
+  Real* seed = (Real*)p; p += field;
+  Real* dphi = (Real*)p; p += field;
+  Real* dT0 = (Real*)p;  p += field;
+  for (int a = 0; a < 2; ++a)
+    for (int sd = 0; sd < 2; ++sd) b.lTw[a][sd] = nullptr;
+  for (int a = 0; a < 2; ++a)
+    if (c->prm.bc[a] == LBM_BC_WALL) {
+      const size_t len = (size_t)(a == 0 ? c->prm.ny : c->prm.nx);
+      for (int sd = 0; sd < 2; ++sd) {
+        b.lTw[a][sd] = (Real*)p;
+        p += align256(len * R);
+        hipError_t e = hipMemsetAsync(b.lTw[a][sd], 0, len * R, c->stream);
+        if (e != hipSuccess) return hip_check(e, "lbm_backward");
+      }
+    }
+  b.nc = node_const<Real>(c);
+  const int f64 = sizeof(Real) == 8;
+  const size_t ss = state_bytes(c);
+  char* snaps = c->tape;
+  char* seg = c->tape + (size_t)c->tape_nsnap * ss;
+  hipError_t e;
+  // seed at the final state (the context's current state)
+  hipLaunchKernelGGL(k_convert, dim3((nxy + 255) / 256), dim3(256), 0, c->stream, (void*)seed, f64,
+                     gphi, gdt == LBM_DT_F64 ? 1 : 0, nxy);
+  {
+    KArgs<Real, Real> a = make_args<Real, Real>(c);
+    e = launch_adj_seed2d(a, b, seed, c->stream);
+    if (e != hipSuccess) return hip_check(e, "adjoint seed");
+  }
+  const int64_t N = c->tape_n, K = c->tape_k;
+  for (int64_t s = c->tape_nsnap - 1; s >= 0; --s) {
+    const int64_t n0 = s * K, n1 = std::min<int64_t>(n0 + K, N);
+    e = hipMemcpyAsync(seg, snaps + (size_t)s * ss, ss, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_check(e, "tape restore");
+    for (int64_t k = 0; k + 1 < n1 - n0; ++k) {   // recompute the segment's states
+      KArgs<Real, Real> a = make_args_blobs<Real, Real>(c, seg + (size_t)k * ss, seg + (size_t)(k + 1) * ss);
+      e = launch_step2d(a, c->ns, c->heat, MODE_STEP, c->stream);
+      if (e != hipSuccess) return hip_check(e, "segment recompute");
+    }
+    for (int64_t k = n1 - n0 - 1; k >= 0; --k) {
+      KArgs<Real, Real> a = make_args_blobs<Real, Real>(c, seg + (size_t)k * ss, nullptr);
+      e = launch_adj_step2d(a, b, c->stream);
+      if (e != hipSuccess) return hip_check(e, "adjoint step");
+    }
+  }
+  {  // initial condition (segment 0's first state is X^0)
+    KArgs<Real, Real> a = make_args_blobs<Real, Real>(c, seg, nullptr);
+    e = launch_adj_init2d(a, b, dphi, dT0, c->stream);
+    if (e != hipSuccess) return hip_check(e, "adjoint init");
+  }
+  const int odt64 = odt == LBM_DT_F64 ? 1 : 0;
+  if (d_phi0)
+    hipLaunchKernelGGL(k_convert, dim3((nxy + 255) / 256), dim3(256), 0, c->stream, d_phi0, odt64,
+                       (const void*)dphi, f64, nxy);
+  if (d_T0)
+    hipLaunchKernelGGL(k_convert, dim3((nxy + 255) / 256), dim3(256), 0, c->stream, d_T0, odt64,
+                       (const void*)dT0, f64, nxy);
+  if (d_Tw) {
+    if (tw_axis < 0 || tw_axis > 1 || tw_side < 0 || tw_side > 1 || !b.lTw[tw_axis][tw_side])
+      return fail(LBM_E_INVAL, "wall face (%d, %d) is not a walled face", tw_axis, tw_side);
+    const long long len = tw_axis == 0 ? c->prm.ny : c->prm.nx;
+    hipLaunchKernelGGL(k_convert, dim3((len + 255) / 256), dim3(256), 0, c->stream, d_Tw, odt64,
+                       (const void*)b.lTw[tw_axis][tw_side], f64, len);
+  }
+  return hip_check(hipGetLastError(), "lbm_backward");
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_tape_size(const lbm_ctx* c, int64_t nsteps, size_t* bytes) {
+  if (!c || !bytes) return fail(LBM_E_INVAL, "NULL argument");
+  if (nsteps < 1) return fail(LBM_E_INVAL, "nsteps must be >= 1");
+  int64_t k, ns;
+  tape_shape(nsteps, k, ns);
+  *bytes = (size_t)(ns + k) * state_bytes(c);
+  return LBM_OK;
+}
+
+lbm_status lbm_forward_taped(lbm_ctx* c, int64_t nsteps, void* tape, size_t bytes) {
+  if (!c || !tape) return fail(LBM_E_INVAL, "NULL argument");
+  lbm_status st = adjoint_supported(c);
+  if (st != LBM_OK) return st;
+  if (!c->initialized) return fail(LBM_E_STATE, "lbm_forward_taped before initialisation");
+  size_t need;
+  st = lbm_tape_size(c, nsteps, &need);
+  if (st != LBM_OK) return st;
+  if (bytes < need) return fail(LBM_E_NOMEM, "tape has %zu bytes, needs %zu", bytes, need);
+  if (((uintptr_t)tape & 255) != 0) return fail(LBM_E_INVAL, "tape must be 256-byte aligned");
+  int64_t k, ns;
+  tape_shape(nsteps, k, ns);
+  const size_t ss = state_bytes(c);
+  char* t = (char*)tape;
+  auto snap = [&](int64_t s) -> hipError_t {
+    char* d = t + (size_t)s * ss;
+    hipError_t e = hipMemcpyAsync(d, c->pops[c->cur], c->L.pops, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d + c->L.pops, c->phip[c->cur], c->L.scal, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d + c->L.pops + c->L.scal, c->qp[c->cur], c->L.scal, hipMemcpyDeviceToDevice,
+                         c->stream);
+    return e;
+  };
+  hipError_t e = snap(0);
+  if (e != hipSuccess) return hip_check(e, "tape snapshot");
+  for (int64_t n = 1; n <= nsteps; ++n) {
+    st = lbm_step(c, 1);
+    if (st != LBM_OK) return st;
+    if (n % k == 0 && n < nsteps) {
+      e = snap(n / k);
+      if (e != hipSuccess) return hip_check(e, "tape snapshot");
+    }
+  }
+  c->tape = t;
+  c->tape_bytes = bytes;
+  c->tape_n = nsteps;
+  c->tape_k = k;
+  c->tape_nsnap = ns;
+  c->tape_end_step = c->step;
+  c->tape_ready = 1;
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_workspace_size(const lbm_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(LBM_E_INVAL, "NULL argument");
+  lbm_status st = adjoint_supported(c);
+  if (st != LBM_OK) return st;
+  *bytes = adj_ws_bytes(c);
+  return LBM_OK;
+}
+
+lbm_status lbm_backward(lbm_ctx* c, const void* dev_gphi, int32_t gphi_dtype, void* dev_ws,
+                        size_t ws_bytes, void* d_phi0, void* d_T0, void* d_Twall, int32_t tw_axis,
+                        int32_t tw_side, int32_t out_dtype) {
+  if (!c || !dev_gphi || !dev_ws) return fail(LBM_E_INVAL, "NULL argument");
+  lbm_status st = adjoint_supported(c);
+  if (st != LBM_OK) return st;
+  if (!c->tape_ready) return fail(LBM_E_STATE, "lbm_backward without lbm_forward_taped");
+  if (c->step != c->tape_end_step)
+    return fail(LBM_E_STATE, "the context stepped after lbm_forward_taped");
+  if (ws_bytes < adj_ws_bytes(c)) return fail(LBM_E_NOMEM, "adjoint workspace too small");
+  if (((uintptr_t)dev_ws & 255) != 0) return fail(LBM_E_INVAL, "workspace must be 256-byte aligned");
+  if ((gphi_dtype != LBM_DT_F32 && gphi_dtype != LBM_DT_F64) ||
+      (out_dtype != LBM_DT_F32 && out_dtype != LBM_DT_F64))
+    return fail(LBM_E_INVAL, "bad dtype");
+  if (c->prm.storage == LBM_ST_F64)
+    return backward_t<double>(c, dev_gphi, gphi_dtype, dev_ws, d_phi0, d_T0, d_Twall, tw_axis, tw_side,
+                              out_dtype);
+  return backward_t<float>(c, dev_gphi, gphi_dtype, dev_ws, d_phi0, d_T0, d_Twall, tw_axis, tw_side,
+                           out_dtype);
+}
 
 }  // extern "C"

@@ -1,0 +1,417 @@
+// Adjoint of the 2-D (D2Q9 x 3) fused step, for gradients of a loss of the
+// final phase field with respect to the initial phase field and the wall
+// temperature (reverse-mode differentiation written by hand; FP32 or FP64).
+//
+// Forward step n maps the stored state X^n = (A: post-collision populations,
+// phi_prev, q_prev) to X^{n+1}.  With lambda = dL/dX, one adjoint step is
+//   K_A  local:   recompute phi, u (LDS, as the forward) and the node inputs,
+//                 apply node_adj: adjoints of the pulled populations P, of
+//                 phi, grad phi, lap phi, u, D at the node; lambda_phi_prev.
+//   K_B  u / D:   transpose of D = div(u phi) (gradient stencil, no-slip and
+//                 Dirichlet ghosts), then the adjoint of the velocity closure.
+//   K_C  phi:     transposed gradient (antisymmetric) and Laplacian
+//                 (symmetric) stencils with Dirichlet ghosts; phi = sum g +
+//                 q_prev/2 distributes lambda_phi to the pulled g and q_prev.
+//   K_D  push:    transpose of the pull gather (each slot of A is read by
+//                 exactly one pull); anti-bounce-back links of s add
+//                 2 w_i lambda to the wall-temperature gradient.
+// Supports at most one walled axis (ghost corners are not differentiated).
+#include "lbm_adjoint.h"
+#include "lbm_adjargs.h"
+#include "lbm_device.h"
+#include "lbm_kernels.h"
+#include "lbm_tile2d.h"
+
+namespace lbm {
+
+template <class Real>
+__device__ inline Real ldp(const Real* p, long long slab, int plane, unsigned node) {
+  return p[(size_t)plane * (size_t)slab + node];
+}
+
+// Global-memory phi with Dirichlet ghosts (one walled axis at most).
+template <class Real, class Store>
+__device__ inline Real phi_g(const KArgs<Real, Store>& a, const Real* fphi, int x, int y) {
+  if (a.wall[1] && (y < 0 || y >= a.ny))
+    return (Real)2 * a.phi_w[1][y < 0 ? 0 : 1] - fphi[(unsigned)(mirror(y, a.ny) * a.px + wrapmod(x, a.nx))];
+  if (a.wall[0] && (x < 0 || x >= a.nx))
+    return (Real)2 * a.phi_w[0][x < 0 ? 0 : 1] - fphi[(unsigned)(wrapmod(y, a.ny) * a.px + mirror(x, a.nx))];
+  return fphi[(unsigned)(wrapmod(y, a.ny) * a.px + wrapmod(x, a.nx))];
+}
+
+// A node-valued adjoint field read at (x, y): 0 beyond a wall (no stencil is
+// evaluated at ghost nodes), periodic wrap otherwise.
+template <class Real, class Store>
+__device__ inline Real lfield(const KArgs<Real, Store>& a, const Real* f, int x, int y) {
+  if (a.wall[1] && (y < 0 || y >= a.ny)) return 0;
+  if (a.wall[0] && (x < 0 || x >= a.nx)) return 0;
+  return f[(unsigned)(wrapmod(y, a.ny) * a.px + wrapmod(x, a.nx))];
+}
+
+// ---------------------------------------------------------------------------
+// K_A: local adjoint
+// ---------------------------------------------------------------------------
+template <class Real>
+__global__ __launch_bounds__(NT2) void k_adj_local2d(const KArgs<Real, Real> a, const AdjArgs<Real> b) {
+  __shared__ Real sphi[R1Y][R1X];
+  __shared__ Real sux[R2Y][R2X];
+  __shared__ Real suy[R2Y][R2X];
+  const int tiles_x = (a.nx + TX2 - 1) / TX2;
+  const int t = blockIdx.x;
+  const int x0 = (t % tiles_x) * TX2, y0 = (t / tiles_x) * TY2;
+  stage2d<Real, Real, true, true, false>(a, sphi, sux, suy, x0, y0);
+  const int tid = threadIdx.x, lx = tid % TX2;
+  for (int r = tid / TX2; r < TY2; r += NT2 / TX2) {
+    const int x = x0 + lx, y = y0 + r;
+    if (x >= a.nx || y >= a.ny) continue;
+    const unsigned node = (unsigned)(y * a.px + x);
+    NodeIn<Real> in;
+    gather2d<D2Q9, 0, false>(a, x, y, in.Pf);
+    gather2d<D2Q9, 1, false>(a, x, y, in.Pg);
+    gather2d<D2Q9, 2, false>(a, x, y, in.Ps);
+    in.phi = sphi[r + 2][lx + 2];
+    Real g3[3];
+    stencil2d<Real, R1X>(sphi, r + 2, lx + 2, g3, in.lphi);
+    in.gphi[0] = g3[0];
+    in.gphi[1] = g3[1];
+    in.u[0] = sux[r + 1][lx + 1];
+    in.u[1] = suy[r + 1][lx + 1];
+    in.D = divergence2d<Real>(sphi, sux, suy, r + 1, lx + 1);
+    in.phip = a.A_phip[node];
+    NodeOut<Real> lo;
+    for (int i = 0; i < 9; ++i) {
+      lo.Af[i] = ldp(b.lA, a.slab, i, node);
+      lo.Ag[i] = ldp(b.lA, a.slab, 9 + i, node);
+      lo.As[i] = ldp(b.lA, a.slab, 18 + i, node);
+    }
+    lo.q = b.lqp[node];
+    NodeAdjIn<Real> li;
+    adj::node_adj(b.nc, in, lo, li);
+    for (int i = 0; i < 9; ++i) {
+      b.lP[(size_t)i * a.slab + node] = li.Pf[i];
+      b.lP[(size_t)(9 + i) * a.slab + node] = li.Pg[i];
+      b.lP[(size_t)(18 + i) * a.slab + node] = li.Ps[i];
+    }
+    // phi_prev of the next state is this step's phi
+    b.lloc[(size_t)LL_PHI * a.slab + node] = li.phi + b.lphip[node];
+    b.lloc[(size_t)LL_GX * a.slab + node] = li.gphi[0];
+    b.lloc[(size_t)LL_GY * a.slab + node] = li.gphi[1];
+    b.lloc[(size_t)LL_LAP * a.slab + node] = li.lphi;
+    b.lloc[(size_t)LL_UX * a.slab + node] = li.u[0];
+    b.lloc[(size_t)LL_UY * a.slab + node] = li.u[1];
+    b.lloc[(size_t)LL_D * a.slab + node] = li.D;
+    b.lphip[node] = li.phip;
+    b.fphi[node] = in.phi;
+    b.fux[node] = in.u[0];
+    b.fuy[node] = in.u[1];
+  }
+}
+
+// Transposed gradient stencil of an adjoint field g_a at (x, y):
+// sum over pairs of 3 w_i c_ia [g_a(x - c_i) - g_a(x + c_i)].
+template <class Real, class Store>
+__device__ inline void grad_T(const KArgs<Real, Store>& a, const Real* gx, const Real* gy, int x,
+                              int y, Real* out) {
+  Real ox = 0, oy = 0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    if (i > D2Q9::opp(i)) continue;
+    const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+    const Real w = (Real)D2Q9::w(i);
+    if (cx && gx) ox += w * (Real)cx * (lfield(a, gx, x - cx, y - cy) - lfield(a, gx, x + cx, y + cy));
+    if (cy && gy) oy += w * (Real)cy * (lfield(a, gy, x - cx, y - cy) - lfield(a, gy, x + cx, y + cy));
+  }
+  out[0] = (Real)3 * ox;
+  out[1] = (Real)3 * oy;
+}
+
+// ---------------------------------------------------------------------------
+// K_B: transpose of D = div(u phi) and the velocity-closure adjoint
+// ---------------------------------------------------------------------------
+template <class Real>
+__global__ __launch_bounds__(256) void k_adj_u2d(const KArgs<Real, Real> a, const AdjArgs<Real> b) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  const unsigned node = (unsigned)(y * a.px + x);
+  const Real* lD = b.lloc + (size_t)LL_D * a.slab;
+  const Real phi = b.fphi[node];
+  const Real u[2] = {b.fux[node], b.fuy[node]};
+  // lambda of P_a = u_a phi at this node
+  Real lPa[2];
+  grad_T(a, lD, lD, x, y, lPa);
+  Real lu[2] = {ldp(b.lloc, a.slab, LL_UX, node) + lPa[0] * phi,
+                ldp(b.lloc, a.slab, LL_UY, node) + lPa[1] * phi};
+  Real lphi = lPa[0] * u[0] + lPa[1] * u[1];
+  // this node as the mirror of a ghost node: P_a(ghost) = -u_a (2 phi_w - phi)
+  for (int ax = 0; ax < 2; ++ax) {
+    if (!a.wall[ax]) continue;
+    const int n = ax == 0 ? a.nx : a.ny, c = ax == 0 ? x : y;
+    for (int side = 0; side < 2; ++side) {
+      if ((side == 0 && c != 0) || (side == 1 && c != n - 1)) continue;
+      const int gx = ax == 0 ? (side == 0 ? -1 : a.nx) : x;
+      const int gy = ax == 1 ? (side == 0 ? -1 : a.ny) : y;
+      Real lPg[2];
+      grad_T(a, lD, lD, gx, gy, lPg);
+      const Real phig = (Real)2 * a.phi_w[ax][side] - phi;
+      for (int k = 0; k < 2; ++k) {
+        lu[k] += -lPg[k] * phig;
+        lphi += lPg[k] * u[k];
+      }
+    }
+  }
+  // velocity closure at this node
+  Real Pf[9];
+  gather2d<D2Q9, 0, false>(a, x, y, Pf);
+  Real P[3][3];
+  for (int j = -1; j <= 1; ++j)
+    for (int i = -1; i <= 1; ++i) P[j + 1][i + 1] = phi_g(a, b.fphi, x + i, y + j);
+  Real g[2] = {0, 0}, l = 0, ws = 0;
+  for (int i = 1; i < 9; ++i) {
+    if (i > D2Q9::opp(i)) continue;
+    const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+    const Real w = (Real)D2Q9::w(i);
+    const Real p = P[1 + cy][1 + cx], m = P[1 - cy][1 - cx];
+    if (cx) g[0] += w * (Real)cx * (p - m);
+    if (cy) g[1] += w * (Real)cy * (p - m);
+    l += w * (p + m);
+    ws += w;
+  }
+  g[0] *= (Real)3;
+  g[1] *= (Real)3;
+  const Real lap = (l - (Real)2 * ws * phi) * (Real)6;
+  Real lPf[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  Real l_phi_u, l_g[2], l_lap;
+  adj::u_adj(b.nc, Pf, phi, g, lap, lu, lPf, l_phi_u, l_g, l_lap);
+  for (int i = 0; i < 9; ++i) b.lP[(size_t)i * a.slab + node] += lPf[i];
+  b.lloc[(size_t)LL_PHI * a.slab + node] += lphi + l_phi_u;
+  b.lloc[(size_t)LL_GX * a.slab + node] += l_g[0];
+  b.lloc[(size_t)LL_GY * a.slab + node] += l_g[1];
+  b.lloc[(size_t)LL_LAP * a.slab + node] += l_lap;
+}
+
+// Transposed stencils for lambda_phi at (x, y) (in-domain or ghost position).
+template <class Real, class Store>
+__device__ inline Real phi_T(const KArgs<Real, Store>& a, const Real* lg_x, const Real* lg_y,
+                             const Real* ll, int x, int y, bool self) {
+  Real g[2];
+  grad_T(a, lg_x, lg_y, x, y, g);
+  Real l = 0, ws = 0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    if (i > D2Q9::opp(i)) continue;
+    const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+    const Real w = (Real)D2Q9::w(i);
+    l += w * (lfield(a, ll, x - cx, y - cy) + lfield(a, ll, x + cx, y + cy));
+    ws += w;
+  }
+  Real out = g[0] + g[1] + (Real)6 * l;
+  if (self) out -= (Real)12 * ws * lfield(a, ll, x, y);
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// K_C: stencil transposes, phi = sum g + q_prev / 2
+// ---------------------------------------------------------------------------
+template <class Real>
+__global__ __launch_bounds__(256) void k_adj_phi2d(const KArgs<Real, Real> a, const AdjArgs<Real> b,
+                                                   Real* lphi_out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  const unsigned node = (unsigned)(y * a.px + x);
+  const Real* lgx = b.lloc + (size_t)LL_GX * a.slab;
+  const Real* lgy = b.lloc + (size_t)LL_GY * a.slab;
+  const Real* ll = b.lloc + (size_t)LL_LAP * a.slab;
+  Real lphi = ldp(b.lloc, a.slab, LL_PHI, node) + phi_T(a, lgx, lgy, ll, x, y, true);
+  // ghosts 2 phi_w - phi(mirror): their transposed value flows back with -1
+  for (int ax = 0; ax < 2; ++ax) {
+    if (!a.wall[ax]) continue;
+    const int n = ax == 0 ? a.nx : a.ny, c = ax == 0 ? x : y;
+    for (int side = 0; side < 2; ++side) {
+      if ((side == 0 && c != 0) || (side == 1 && c != n - 1)) continue;
+      const int gx = ax == 0 ? (side == 0 ? -1 : a.nx) : x;
+      const int gy = ax == 1 ? (side == 0 ? -1 : a.ny) : y;
+      lphi -= phi_T(a, lgx, lgy, ll, gx, gy, false);
+    }
+  }
+  if (lphi_out) {   // initial-condition adjoint: lambda of phi0 itself
+    lphi_out[(unsigned)(y * a.nx + x)] = lphi;
+    return;
+  }
+  for (int i = 0; i < 9; ++i) b.lP[(size_t)(9 + i) * a.slab + node] += lphi;
+  b.lqp[node] = (Real)0.5 * lphi;
+}
+
+// ---------------------------------------------------------------------------
+// K_D: transpose of the pull gather
+// ---------------------------------------------------------------------------
+template <class Real>
+__global__ __launch_bounds__(256) void k_adj_push2d(const KArgs<Real, Real> a, const AdjArgs<Real> b) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  const unsigned node = (unsigned)(y * a.px + x);
+  Real tw[2][2] = {{0, 0}, {0, 0}};
+  for (int fam = 0; fam < 3; ++fam) {
+    for (int j = 0; j < 9; ++j) {
+      const int cx = D2Q9::cx(j), cy = D2Q9::cy(j);
+      int yx = x + cx, yy = y + cy;
+      const bool oy = cy != 0 && a.wall[1] && (yy < 0 || yy >= a.ny);
+      const bool ox = cx != 0 && !oy && a.wall[0] && (yx < 0 || yx >= a.nx);
+      Real v;
+      if (oy || ox) {
+        const int i = D2Q9::opp(j);
+        const Real lp = b.lP[(size_t)(fam * 9 + i) * a.slab + node];
+        v = fam == 0 ? lp : -lp;
+        if (fam == 2) {
+          const int ax = oy ? 1 : 0;
+          const int side = oy ? (yy < 0 ? 0 : 1) : (yx < 0 ? 0 : 1);
+          tw[ax][side] += (Real)2 * (Real)D2Q9::w(i) * lp;
+        }
+      } else {
+        if (!a.wall[0]) yx = wrap1(yx, a.nx);
+        if (!a.wall[1]) yy = wrap1(yy, a.ny);
+        v = b.lP[(size_t)(fam * 9 + j) * a.slab + (unsigned)(yy * a.px + yx)];
+      }
+      b.lA[(size_t)(fam * 9 + j) * a.slab + node] = v;
+    }
+  }
+  for (int ax = 0; ax < 2; ++ax)
+    for (int side = 0; side < 2; ++side)
+      if (b.lTw[ax][side] && tw[ax][side] != (Real)0) b.lTw[ax][side][ax == 1 ? x : y] += tw[ax][side];
+}
+
+// Seed: loss of the final phase field with dL/dphi^N = gphi (field
+// [ny][nx] of Real).  phi^N = sum g (pulled) + q_prev / 2.
+template <class Real>
+__global__ void k_adj_seed2d(const KArgs<Real, Real> a, const AdjArgs<Real> b, const Real* gphi) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  const unsigned node = (unsigned)(y * a.px + x);
+  const Real gv = gphi[(unsigned)(y * a.nx + x)];
+  for (int i = 0; i < 27; ++i) b.lP[(size_t)i * a.slab + node] = (i >= 9 && i < 18) ? gv : (Real)0;
+  b.lphip[node] = 0;
+  b.lqp[node] = (Real)0.5 * gv;
+}
+
+// Initial-condition adjoint, local part.  The initial state is the pull
+// pre-image of the barred equilibria at (phi0, T0) with u = 0: lambda of
+// those post-streaming values is the pull of lambda_A (anti-bounce-back
+// slots also carry 2 w_i T_w).  phi0 = phi_prev^0, T0 = sum of the pulled s.
+template <class Real>
+__global__ __launch_bounds__(256) void k_adj_init_local2d(const KArgs<Real, Real> a,
+                                                          const AdjArgs<Real> b, Real* lT0_out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  const unsigned node = (unsigned)(y * a.px + x);
+  // lambda of the post-streaming init values: pull of lambda_A
+  NodeOut<Real> lo;
+  Real* lsets[3] = {lo.Af, lo.Ag, lo.As};
+  Real tw[2][2] = {{0, 0}, {0, 0}};
+  for (int fam = 0; fam < 3; ++fam)
+    for (int i = 0; i < 9; ++i) {
+      const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+      int sx = x - cx, sy = y - cy;
+      const bool oy = cy != 0 && a.wall[1] && (sy < 0 || sy >= a.ny);
+      const bool ox = cx != 0 && !oy && a.wall[0] && (sx < 0 || sx >= a.nx);
+      if (oy || ox) {
+        const int j = D2Q9::opp(i);
+        const Real la = b.lA[(size_t)(fam * 9 + j) * a.slab + node];
+        lsets[fam][i] = fam == 0 ? la : -la;
+        if (fam == 2) {
+          const int ax = oy ? 1 : 0;
+          const int side = oy ? (sy < 0 ? 0 : 1) : (sx < 0 ? 0 : 1);
+          tw[ax][side] += (Real)2 * (Real)D2Q9::w(i) * la;
+        }
+      } else {
+        if (!a.wall[0]) sx = wrap1(sx, a.nx);
+        if (!a.wall[1]) sy = wrap1(sy, a.ny);
+        lsets[fam][i] = b.lA[(size_t)(fam * 9 + i) * a.slab + (unsigned)(sy * a.px + sx)];
+      }
+    }
+  lo.q = b.lqp[node];
+  for (int ax = 0; ax < 2; ++ax)
+    for (int side = 0; side < 2; ++side)
+      if (b.lTw[ax][side] && tw[ax][side] != (Real)0) b.lTw[ax][side][ax == 1 ? x : y] += tw[ax][side];
+  // forward init inputs: phi0 and its stencils, T0
+  const Real phi = a.A_phip[node];
+  Real P[3][3];
+  for (int j = -1; j <= 1; ++j)
+    for (int i = -1; i <= 1; ++i) P[j + 1][i + 1] = phi_g(a, a.A_phip, x + i, y + j);
+  Real g[2] = {0, 0}, l = 0, ws = 0;
+  for (int i = 1; i < 9; ++i) {
+    if (i > D2Q9::opp(i)) continue;
+    const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+    const Real w = (Real)D2Q9::w(i);
+    const Real p = P[1 + cy][1 + cx], m = P[1 - cy][1 - cx];
+    if (cx) g[0] += w * (Real)cx * (p - m);
+    if (cy) g[1] += w * (Real)cy * (p - m);
+    l += w * (p + m);
+    ws += w;
+  }
+  g[0] *= (Real)3;
+  g[1] *= (Real)3;
+  const Real lap = (l - (Real)2 * ws * phi) * (Real)6;
+  Real Ps[9];
+  gather2d<D2Q9, 2, false>(a, x, y, Ps);
+  Real T = 0;
+  for (int i = 0; i < 9; ++i) T += Ps[i];
+  Real l_phi, l_g[2], l_lap, l_T;
+  adj::init_adj(b.nc, phi, g, lap, T, lo, l_phi, l_g, l_lap, l_T);
+  b.lloc[(size_t)LL_PHI * a.slab + node] = l_phi + b.lphip[node];
+  b.lloc[(size_t)LL_GX * a.slab + node] = l_g[0];
+  b.lloc[(size_t)LL_GY * a.slab + node] = l_g[1];
+  b.lloc[(size_t)LL_LAP * a.slab + node] = l_lap;
+  if (lT0_out) lT0_out[(unsigned)(y * a.nx + x)] = l_T;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <class Real>
+static dim3 node_grid(const KArgs<Real, Real>& a) {
+  return dim3((a.nx + 255) / 256, a.ny);
+}
+
+template <class Real>
+hipError_t launch_adj_step2d_t(const KArgs<Real, Real>& a, const AdjArgs<Real>& b, hipStream_t st) {
+  const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + TY2 - 1) / TY2);
+  hipLaunchKernelGGL(k_adj_local2d<Real>, dim3(tiles), dim3(NT2), 0, st, a, b);
+  hipLaunchKernelGGL(k_adj_u2d<Real>, node_grid(a), dim3(256), 0, st, a, b);
+  hipLaunchKernelGGL(k_adj_phi2d<Real>, node_grid(a), dim3(256), 0, st, a, b, (Real*)nullptr);
+  hipLaunchKernelGGL(k_adj_push2d<Real>, node_grid(a), dim3(256), 0, st, a, b);
+  return hipGetLastError();
+}
+
+template <class Real>
+hipError_t launch_adj_seed2d_t(const KArgs<Real, Real>& a, const AdjArgs<Real>& b, const Real* gphi,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_seed2d<Real>, node_grid(a), dim3(256), 0, st, a, b, gphi);
+  hipLaunchKernelGGL(k_adj_push2d<Real>, node_grid(a), dim3(256), 0, st, a, b);
+  return hipGetLastError();
+}
+
+template <class Real>
+hipError_t launch_adj_init2d_t(const KArgs<Real, Real>& a, const AdjArgs<Real>& b, Real* dphi0,
+                               Real* dT0, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_init_local2d<Real>, node_grid(a), dim3(256), 0, st, a, b, dT0);
+  hipLaunchKernelGGL(k_adj_phi2d<Real>, node_grid(a), dim3(256), 0, st, a, b, dphi0);
+  return hipGetLastError();
+}
+
+#define LBM_ADJ_INST(REAL)                                                                    \
+  hipError_t launch_adj_step2d(const KArgs<REAL, REAL>& a, const AdjArgs<REAL>& b,             \
+                               hipStream_t st) {                                              \
+    return launch_adj_step2d_t<REAL>(a, b, st);                                               \
+  }                                                                                           \
+  hipError_t launch_adj_seed2d(const KArgs<REAL, REAL>& a, const AdjArgs<REAL>& b,             \
+                               const REAL* g, hipStream_t st) {                               \
+    return launch_adj_seed2d_t<REAL>(a, b, g, st);                                            \
+  }                                                                                           \
+  hipError_t launch_adj_init2d(const KArgs<REAL, REAL>& a, const AdjArgs<REAL>& b, REAL* dphi0, \
+                               REAL* dT0, hipStream_t st) {                                   \
+    return launch_adj_init2d_t<REAL>(a, b, dphi0, dT0, st);                                   \
+  }
+LBM_ADJ_INST(float)
+LBM_ADJ_INST(double)
+#undef LBM_ADJ_INST
+
+}  // namespace lbm

@@ -77,6 +77,19 @@ LBM_DECL(__hip_bfloat16, float)
 int step2d_blocks(int nx, int ny);
 int step3d_blocks(int nx, int ny, int nz);
 
+namespace adj { template <class Real> struct NodeConst; }
+template <class Real> struct AdjArgs;
+#define LBM_ADJ_DECL(REAL)                                                                    \
+  hipError_t launch_adj_step2d(const KArgs<REAL, REAL>& a, const AdjArgs<REAL>& b,             \
+                               hipStream_t st);                                               \
+  hipError_t launch_adj_seed2d(const KArgs<REAL, REAL>& a, const AdjArgs<REAL>& b,             \
+                               const REAL* g, hipStream_t st);                                \
+  hipError_t launch_adj_init2d(const KArgs<REAL, REAL>& a, const AdjArgs<REAL>& b, REAL* dphi0, \
+                               REAL* dT0, hipStream_t st);
+LBM_ADJ_DECL(float)
+LBM_ADJ_DECL(double)
+#undef LBM_ADJ_DECL
+
 // Sum the per-block partials in a fixed order into out[NPART] (device).
 hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st);
 

@@ -1,0 +1,237 @@
+// 2-D tile machinery shared by the forward step and its adjoint: pulls with
+// wall links, the directional-derivative stencils, div(u phi), and the
+// LDS staging of phi (tile + 2-halo) and u (tile + 1-halo).
+#pragma once
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+constexpr int TX2 = 64, TY2 = 32, NT2 = 256;
+constexpr int R1X = TX2 + 4, R1Y = TY2 + 4;   // phi region (halo 2)
+constexpr int R2X = TX2 + 2, R2Y = TY2 + 2;   // u region (halo 1)
+
+// Pull the Q populations of family FAM (0 f, 1 g, 2 s) arriving at node
+// (x, y).  A link whose source lies beyond a wall reflects at the node:
+// bounce-back for f, anti-bounce-back -v_{i'} + 2 w_i V_w for g and s
+// (Sec. 3.3).  The y wall takes precedence over the x wall at corners.
+// FAST: the caller guarantees that no source node of this tile lies beyond
+// a wall or across a periodic seam, so every pull is the uniform plane
+// pointer shifted by -(c_x + c_y px) and indexed by the node's lane offset.
+template <class Lat, int FAM, bool FAST = false, class Real, class Store>
+__device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real* v) {
+  using C = Codec<Real, Store>;
+  const int off = FAM == 0 ? a.off_f : (FAM == 1 ? a.off_g : a.off_s);
+  const Real ref = a.ref[FAM], inv = a.inv_scale[FAM];
+  // uniform plane base (scalar registers) + 32-bit lane offset
+  const Store* __restrict__ base = a.A + (size_t)off * (size_t)a.slab;
+  const unsigned node = (unsigned)(y * a.px + x);
+  if constexpr (FAST) {
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i) {
+      const unsigned sl = (unsigned)i * (unsigned)a.slab - (unsigned)(Lat::cx(i) + Lat::cy(i) * a.px);
+      v[i] = C::dec(ld_fam(base, node + sl), (Real)Lat::w(i) * ref, inv);
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i) {
+    const int cx = Lat::cx(i), cy = Lat::cy(i);
+    int sx = x - cx, sy = y - cy;
+    const bool oy = (cy != 0) && a.wall[1] && (sy < 0 || sy >= a.ny);
+    const bool ox = (cx != 0) && !oy && a.wall[0] && (sx < 0 || sx >= a.nx);
+    const Real wref = (Real)Lat::w(i) * ref;
+    if (oy || ox) {
+      const int j = Lat::opp(i);
+      Real r = C::dec(ld_fam(base, (unsigned)j * (unsigned)a.slab + node), wref, inv);
+      if (FAM != 0) {
+        Real V;
+        if (oy) {
+          const int side = sy < 0 ? 0 : 1;
+          V = FAM == 1 ? a.phi_w[1][side] : a.Tw[1][side][x];
+        } else {
+          const int side = sx < 0 ? 0 : 1;
+          V = FAM == 1 ? a.phi_w[0][side] : a.Tw[0][side][y];
+        }
+        r = -r + (Real)2 * (Real)Lat::w(i) * V;
+      }
+      v[i] = r;
+    } else {
+      if (cx != 0 && !a.wall[0]) sx = wrap1(sx, a.nx);
+      if (cy != 0 && !a.wall[1]) sy = wrap1(sy, a.ny);
+      v[i] = C::dec(ld_fam(base, (unsigned)i * (unsigned)a.slab + (unsigned)(sy * a.px + sx)), wref, inv);
+    }
+  }
+}
+
+// Store the Q post-collision populations of one family at `node` of B.
+template <class Lat, class Real, class Store>
+__device__ inline void store_family(const KArgs<Real, Store>& a, int off, int fam, unsigned node,
+                                    const Real* v) {
+  using C = Codec<Real, Store>;
+  Store* __restrict__ base = a.B + (size_t)off * (size_t)a.slab;
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i)
+    st_fam(base, (unsigned)i * (unsigned)a.slab + node,
+           C::enc(v[i], (Real)Lat::w(i) * a.ref[fam], a.scale[fam]));
+}
+
+// Directional-derivative gradient and Laplacian (Eqs. DerivDirec_Grad, Grad,
+// DerivDirect_Laplacian, Laplacian) of an LDS field at (ry, rx).  The sums
+// run over the D2Q9 directions; a direction and its opposite contribute the
+// same term, so each pair is taken once with weight 2 (exact rewrite).
+template <class Real, int RX>
+__device__ inline void stencil2d(const Real (*s)[RX], int ry, int rx, Real* g, Real& lap) {
+  const Real c = s[ry][rx];
+  Real gx = 0, gy = 0, l = 0, wsum = 0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    if (i > D2Q9::opp(i)) continue;
+    const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+    const Real w = (Real)D2Q9::w(i);
+    const Real p = s[ry + cy][rx + cx], m = s[ry - cy][rx - cx];
+    if (cx) gx += w * (Real)cx * (p - m);
+    if (cy) gy += w * (Real)cy * (p - m);
+    l += w * (p + m);
+    wsum += w;
+  }
+  g[0] = gx * (Real)3;   // 1/c_s^2
+  g[1] = gy * (Real)3;
+  g[2] = 0;
+  lap = (l - (Real)2 * wsum * c) * (Real)6;
+}
+
+// div(u phi): the Eq. Grad stencil applied to u_a phi, a-th component, summed.
+template <class Real>
+__device__ inline Real divergence2d(const Real (*sphi)[R1X], const Real (*sux)[R2X],
+                                    const Real (*suy)[R2X], int ry2, int rx2) {
+  Real d = 0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    if (i > D2Q9::opp(i)) continue;
+    const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+    const Real w = (Real)D2Q9::w(i);
+    const Real pp = sphi[ry2 + 1 + cy][rx2 + 1 + cx], pm = sphi[ry2 + 1 - cy][rx2 + 1 - cx];
+    if (cx != 0)
+      d += w * (Real)cx * (sux[ry2 + cy][rx2 + cx] * pp - sux[ry2 - cy][rx2 - cx] * pm);
+    if (cy != 0)
+      d += w * (Real)cy * (suy[ry2 + cy][rx2 + cx] * pp - suy[ry2 - cy][rx2 - cx] * pm);
+  }
+  return d * (Real)3;
+}
+
+// Map a region coordinate to the domain: wraps periodic axes; returns false
+// for points beyond a wall (ghosts).
+__device__ inline bool to_domain(int& g, int n, int wall) {
+  if (wall) return g >= 0 && g < n;
+  g = wrapmod(g, n);
+  return true;
+}
+
+// Mirror of a ghost coordinate across the half-way wall (-1 <-> 0, n <-> n-1).
+__device__ inline int mirror(int g, int n) { return g < 0 ? -1 - g : 2 * n - 1 - g; }
+
+// Stage phi on the tile + 2-halo and (NS && HEAT) u on the tile + 1-halo in
+// LDS, with wall ghosts (x ghosts first, then y ghosts, so corners compose).
+template <class Store, class Real, bool NS, bool HEAT, bool FAST>
+__device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi)[R1X],
+                                        Real (*sux)[R2X], Real (*suy)[R2X], int x0, int y0) {
+  const int tid = threadIdx.x;
+  // ---- phase 1: phi on the tile + 2-halo --------------------------------
+  for (int k = tid; k < R1X * R1Y; k += NT2) {
+    const int ry = k / R1X, rx = k - ry * R1X;
+    int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
+    Real v = 0;
+    if (FAST || (to_domain(gx, a.nx, a.wall[0]) && to_domain(gy, a.ny, a.wall[1]))) {
+      Real g[9];
+      gather2d<D2Q9, 1, FAST>(a, gx, gy, g);
+      Real s = 0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) s += g[i];
+      v = s + (Real)0.5 * (Real)ld_plane(a.A_qp, (unsigned)(gy * a.px + gx));
+    }
+    sphi[ry][rx] = v;
+  }
+  __syncthreads();
+  if (!FAST && a.wall[0]) {   // x ghosts first, then y ghosts (corners compose)
+    for (int k = tid; k < R1X * R1Y; k += NT2) {
+      const int ry = k / R1X, rx = k - ry * R1X;
+      const int gx = x0 - 2 + rx;
+      if (gx < 0 || gx >= a.nx) {
+        const int mx = mirror(gx, a.nx) - (x0 - 2);
+        if (mx >= 0 && mx < R1X) sphi[ry][rx] = (Real)2 * a.phi_w[0][gx < 0 ? 0 : 1] - sphi[ry][mx];
+      }
+    }
+    __syncthreads();
+  }
+  if (!FAST && a.wall[1]) {
+    for (int k = tid; k < R1X * R1Y; k += NT2) {
+      const int ry = k / R1X, rx = k - ry * R1X;
+      const int gy = y0 - 2 + ry;
+      if (gy < 0 || gy >= a.ny) {
+        const int my = mirror(gy, a.ny) - (y0 - 2);
+        if (my >= 0 && my < R1Y) sphi[ry][rx] = (Real)2 * a.phi_w[1][gy < 0 ? 0 : 1] - sphi[my][rx];
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- phase 2: u on the tile + 1-halo -----------------------------------
+  if constexpr (NS && HEAT) {
+    for (int k = tid; k < R2X * R2Y; k += NT2) {
+      const int ry = k / R2X, rx = k - ry * R2X;
+      int gx = x0 - 1 + rx, gy = y0 - 1 + ry;
+      Real ux = 0, uy = 0;
+      if (FAST || (to_domain(gx, a.nx, a.wall[0]) && to_domain(gy, a.ny, a.wall[1]))) {
+        Real gphi[3], lphi, rho, mu, F[3];
+        stencil2d<Real, R1X>(sphi, ry + 1, rx + 1, gphi, lphi);
+        forces(a, sphi[ry + 1][rx + 1], gphi, lphi, rho, mu, F);
+        Real f[9];
+        gather2d<D2Q9, 0, FAST>(a, gx, gy, f);
+        Real mx = 0, my = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          if (D2Q9::cx(i)) mx += (Real)D2Q9::cx(i) * f[i];
+          if (D2Q9::cy(i)) my += (Real)D2Q9::cy(i) * f[i];
+        }
+        const Real ir = (Real)1 / rho;
+        ux = ((Real)3 * mx + (Real)0.5 * F[0]) * ir;
+        uy = ((Real)3 * my + (Real)0.5 * F[1]) * ir;
+      }
+      sux[ry][rx] = ux;
+      suy[ry][rx] = uy;
+    }
+    __syncthreads();
+    if (!FAST && a.wall[0]) {
+      for (int k = tid; k < R2X * R2Y; k += NT2) {
+        const int ry = k / R2X, rx = k - ry * R2X;
+        const int gx = x0 - 1 + rx;
+        if (gx < 0 || gx >= a.nx) {
+          const int mx = mirror(gx, a.nx) - (x0 - 1);
+          if (mx >= 0 && mx < R2X) {
+            sux[ry][rx] = -sux[ry][mx];
+            suy[ry][rx] = -suy[ry][mx];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (!FAST && a.wall[1]) {
+      for (int k = tid; k < R2X * R2Y; k += NT2) {
+        const int ry = k / R2X, rx = k - ry * R2X;
+        const int gy = y0 - 1 + ry;
+        if (gy < 0 || gy >= a.ny) {
+          const int my = mirror(gy, a.ny) - (y0 - 1);
+          if (my >= 0 && my < R2Y) {
+            sux[ry][rx] = -sux[my][rx];
+            suy[ry][rx] = -suy[my][rx];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+}
+
+}  // namespace lbm

@@ -76,6 +76,10 @@ def load_library(path: str = LIB_PATH):
         "lbm_set_state": (I32, [P, P, SZ]),
         "lbm_get_step": (I32, [P, C.POINTER(I64)]),
         "lbm_sync": (I32, [P]),
+        "lbm_tape_size": (I32, [P, I64, C.POINTER(SZ)]),
+        "lbm_forward_taped": (I32, [P, I64, P, SZ]),
+        "lbm_adjoint_workspace_size": (I32, [P, C.POINTER(SZ)]),
+        "lbm_backward": (I32, [P, P, I32, P, SZ, P, P, P, I32, I32, I32]),
         "lbm_destroy": (None, [P]),
         "lbm_last_error": (C.c_char_p, []),
         "lbm_version": (C.c_char_p, []),
@@ -242,6 +246,41 @@ class Sim:
 
     def sync(self):
         _check(self.lib.lbm_sync(self.ctx))
+
+    # -- adjoint -----------------------------------------------------------
+    @staticmethod
+    def _aligned(n: int, device):
+        import torch
+        t = torch.empty(n + 256, dtype=torch.uint8, device=device)
+        off = (-t.data_ptr()) % 256
+        return t, t.data_ptr() + off
+
+    def forward_taped(self, nsteps: int):
+        """Advance nsteps recording the sqrt(T) tape for backward()."""
+        n = C.c_size_t()
+        _check(self.lib.lbm_tape_size(self.ctx, int(nsteps), C.byref(n)))
+        self._tape, ptr = self._aligned(n.value, self.device)
+        _check(self.lib.lbm_forward_taped(self.ctx, int(nsteps), C.c_void_p(ptr), n))
+        return self
+
+    def backward(self, gphi, tw_face=(1, 0)) -> dict:
+        """Gradients of a loss with dL/dphi^N = gphi (array [ny][nx]) with
+        respect to phi0, T0 and the wall-temperature face tw_face."""
+        torch = self.torch
+        g = self._dev(gphi, torch.float64).reshape(self.shape[1:]).contiguous()
+        n = C.c_size_t()
+        _check(self.lib.lbm_adjoint_workspace_size(self.ctx, C.byref(n)))
+        ws, ptr = self._aligned(n.value, self.device)
+        nx, ny = self.prm["nx"], self.prm["ny"]
+        dphi = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+        dT0 = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+        face_len = nx if tw_face[0] == 1 else ny
+        dTw = torch.empty(face_len, dtype=torch.float64, device=self.device)
+        _check(self.lib.lbm_backward(self.ctx, self._ptr(g), LBM_DT_F64, C.c_void_p(ptr), n,
+                                     self._ptr(dphi), self._ptr(dT0), self._ptr(dTw),
+                                     int(tw_face[0]), int(tw_face[1]), LBM_DT_F64))
+        self._keep_ws = ws
+        return dict(phi0=dphi, T0=dT0, Tw=dTw)
 
     @property
     def steps_taken(self) -> int:
