@@ -76,6 +76,46 @@ def time_variant(prm, fields, storage, steps, warmup):
                 nodes=n, finite=diag["nonfinite"] == 0)
 
 
+def adjoint_ratio(nx=512, ny=512, nsteps=200):
+    """Time of the reverse sweep per step (segment recompute included) over
+    the forward step time, FP32, film recipe at 512 x 512."""
+    import numpy as np
+    import torch
+    from paper_2003_06342_amd import inputs as I
+    from paper_2003_06342_amd import lbm
+    prm = I.film2d_params(nx, ny)
+    phi0, T0, _ = I.film2d_fields(prm, seed=2, h0=32.0, amp=2.0)
+    sim = lbm.Sim(prm, "f32")
+    sim.set_wall_T(1, 0, I.wall_T_row(nx, seed=3))
+    sim.init(phi0, T0)
+    sim.step(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(nsteps)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / nsteps
+    sim.init(phi0, T0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.forward_taped(nsteps)
+    torch.cuda.synchronize()
+    t_tape = (time.perf_counter() - t0) / nsteps
+    g = np.full((ny, nx), 1.0 / (nx * ny))
+    sim.backward(g)   # warm-up of the adjoint kernels
+    torch.cuda.synchronize()
+    sim.init(phi0, T0)
+    sim.forward_taped(nsteps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.backward(g)
+    torch.cuda.synchronize()
+    t_bwd = (time.perf_counter() - t0) / nsteps
+    sim.close()
+    return dict(grid=f"{nx}x{ny}", steps=nsteps, fwd_ms=round(1e3 * t_fwd, 4),
+                taped_fwd_ms=round(1e3 * t_tape, 4), bwd_ms_per_step=round(1e3 * t_bwd, 4),
+                ratio_with_recompute=round(t_bwd / t_fwd, 3))
+
+
 def cpu_baseline(prm, fields, budget_s=20.0):
     """FP64 oracle on the same grid for as many whole steps as fit ~budget_s."""
     import torch
@@ -113,6 +153,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build targets one GPU; --gpus {args.gpus} is not supported "
@@ -148,13 +190,36 @@ def main():
         out["warning"] = "non-finite values after the timed run"
     if not args.no_variants:
         var = {}
+
+        def record(name, prm_v, fields_v, st, q, steps, warm):
+            r = time_variant(prm_v, fields_v, st, steps, warm)
+            b = bytes_per_node(prm_v["dim"], q, st)
+            var[name] = dict(mlups=round(r["mlups"], 1), kernel_ms=round(r["kernel_ms"], 5),
+                             bytes_per_node=b,
+                             hbm_frac=round(b * r["nodes"] / (r["kernel_ms"] * 1e-3) / 1e9
+                                            / HBM_PEAK_GBS, 4))
         for st in ("f64", "f16dev", "bf16dev"):
-            r = time_variant(prm, fields, st, max(20, args.steps // 4), 5)
-            b = bytes_per_node(2, 27, st)
-            var[f"film2d_{st}"] = dict(mlups=round(r["mlups"], 1), kernel_ms=round(r["kernel_ms"], 5),
-                                       hbm_frac=round(b * r["nodes"] / (r["kernel_ms"] * 1e-3) / 1e9
-                                                      / HBM_PEAK_GBS, 4))
+            record(f"film2d_1024x2048_{st}", prm, fields, st, 27, max(20, args.steps // 4), 5)
+        p3 = I.film3d_params(256)
+        f3 = I.film3d_fields(p3, seed=1, h0=32.0, amp=3.0)
+        record("film3d_256^3_f32", p3, f3, "f32", 33, 20, 3)
+        p5 = I.film3d_params(512)
+        f5 = I.film3d_fields(p5, seed=5, h0=64.0, amp=6.0)
+        for st in ("f32", "f16dev", "bf16dev"):
+            record(f"film3d_512^3_{st}", p5, f5, st, 33, 10, 2)
+        del f5
+        try:
+            var["adjoint_512x512_f32"] = adjoint_ratio()
+        except Exception as e:  # report, do not hide the headline
+            var["adjoint_512x512_f32"] = {"error": str(e)}
         out["variants"] = var
+    if args.copy_calib:
+        x = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = x.numel()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prm, fields)
     print(json.dumps(out), flush=True)

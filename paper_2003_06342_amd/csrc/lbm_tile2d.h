@@ -7,7 +7,7 @@
 
 namespace lbm {
 
-constexpr int TX2 = 64, TY2 = 32, NT2 = 256;
+constexpr int TX2 = 64, TY2 = 64, NT2 = 512;
 constexpr int R1X = TX2 + 4, R1Y = TY2 + 4;   // phi region (halo 2)
 constexpr int R2X = TX2 + 2, R2Y = TY2 + 2;   // u region (halo 1)
 

@@ -88,13 +88,16 @@ def test_adjoint_sqrtT_segments_match_oracle():
     assert e_phi < 1e-9 and e_tw < 1e-9
 
 
-def test_adjoint_vs_central_fd_config4_size():
+@pytest.mark.parametrize("n", [1000, 2000])
+def test_adjoint_vs_central_fd_config4_size(n):
     """512 x 512 film (lambda = 512 gravity, h = 32 + 2 cos + noise, T_w ~
     N(1, 0.05^2)), FP64: directional derivatives of V along 16 random unit
-    directions of T_w and of phi0 vs central differences of the forward."""
+    directions of T_w and of phi0 vs central differences of the forward.
+    The film's derivatives grow by about 1e3 between steps 1000 and 2000
+    (the vapour-side sharpening instability), so the central difference
+    needs a step in the linear regime (eps = 1e-6)."""
     need_gpu()
     nx = ny = 512
-    n = 2000
     prm = I.film2d_params(nx, ny)
     phi0, T0, _ = I.film2d_fields(prm, seed=2, h0=32.0, amp=2.0)
     Tw = I.wall_T_row(nx, seed=3)
@@ -108,13 +111,13 @@ def test_adjoint_vs_central_fd_config4_size():
         for kind in ("Tw", "phi0"):
             if kind == "Tw":
                 v = dirs_tw[k]
-                eps = 1e-3
+                eps = 1e-6
                 Vp = gpu_value(prm, phi0, T0, Tw + eps * v, n)
                 Vm = gpu_value(prm, phi0, T0, Tw - eps * v, n)
                 ad = float(np.dot(g["Tw"], v))
             else:
                 v = dirs_phi[k].reshape(phi0.shape)
-                eps = 1e-3
+                eps = 1e-6
                 Vp = gpu_value(prm, phi0 + eps * v, T0, Tw, n)
                 Vm = gpu_value(prm, phi0 - eps * v, T0, Tw, n)
                 ad = float(np.sum(g["phi0"] * v[0]))
