@@ -214,10 +214,17 @@ def main():
             var["adjoint_512x512_f32"] = {"error": str(e)}
         out["variants"] = var
     if args.copy_calib:
+        # 512 MiB device copy (16-byte accesses), then a scaled copy of a float
+        # view offset by one element, which cannot be vectorised (4-byte
+        # accesses per lane, like the populations in the step kernels)
         x = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
             y.copy_(x)
+        xf, yf = x.view(torch.float32), y.view(torch.float32)
+        xf.fill_(1.0)
+        for _ in range(3):
+            torch.mul(xf[1:], 2.0, out=yf[1:])
         torch.cuda.synchronize()
         out["copy_calib_bytes"] = x.numel()
     if not args.no_cpu:

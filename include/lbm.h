@@ -113,7 +113,8 @@ typedef struct {
 lbm_status lbm_workspace_size(const lbm_params* prm, size_t* bytes);
 
 /* Validate the parameters (tau > 0, omega = 1/(tau + 1/2) < 2 for the
- * extreme phases, rho > 0, W > 0, lattice/dimension pairs) and build a
+ * extreme phases, rho > 0, W > 0, lattice/dimension pairs, at least 2 nodes
+ * along a walled axis) and build a
  * context that uses `dev_workspace` (>= lbm_workspace_size bytes, 256-byte
  * aligned, owned by the caller) and launches on `hip_stream` (a
  * hipStream_t; NULL = the null stream).  *out is NULL on failure. */

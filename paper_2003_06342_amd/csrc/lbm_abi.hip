@@ -88,6 +88,9 @@ lbm_status validate(const lbm_params* p) {
     if (p->nz != 1) return fail(LBM_E_INVAL, "2-D needs nz == 1");
     if (p->lat_f != LBM_D2Q9 || p->lat_g != LBM_D2Q9 || p->lat_s != LBM_D2Q9)
       return fail(LBM_E_UNSUPPORTED, "2-D supports D2Q9 for f, g and s");
+    // the 2-halo ghost beyond a wall mirrors the second node from it
+    if ((p->bc[0] == LBM_BC_WALL && p->nx < 2) || (p->bc[1] == LBM_BC_WALL && p->ny < 2))
+      return fail(LBM_E_INVAL, "a walled axis needs at least 2 nodes");
   } else {
     if (p->lat_f != LBM_D3Q19 || p->lat_g != LBM_D3Q7 || p->lat_s != LBM_D3Q7)
       return fail(LBM_E_UNSUPPORTED, "3-D supports D3Q19 (f) with D3Q7 (g, s)");

@@ -1,6 +1,6 @@
 // 2-D fused time step (D2Q9 for f, g and s; D2Q9 stencils) for gfx950.
 //
-// One workgroup (256 lanes, 4 wave64) owns a 64 x 16 tile and runs three
+// One workgroup (512 lanes, 8 wave64) owns a 64 x 64 tile and runs three
 // LDS phases per step:
 //   1. phi = sum g_bar + q_prev/2 (Eq. Moment_Phi, lagged production) on the
 //      tile plus a 2-node halo, pulled straight from buffer A with the wall
@@ -13,9 +13,12 @@
 //      d_t phi, div(u phi) from LDS, production (Eq. ProductionRate),
 //      equilibria, sources, BGK collision; write to buffer B (pull scheme:
 //      the next step's gather does the streaming).
-// The halo recomputation keeps every step a single pass over HBM: each
-// population is read once from A and written once to B (halo re-reads hit
-// L2), plus phi_prev and q_prev.
+// The halo recomputation keeps every step one kernel with no grid-wide
+// synchronisation.  Each population is written once to B.  g and f are
+// pulled twice from A (phases 1-2 and phase 3).  A workgroup's tile is far
+// larger than its share of L2, so the second pull comes from HBM again.
+// The L2-to-memory read requests of one step on the 1024 x 2048 film come
+// to 1.8 times the populations' size.
 #include "lbm_device.h"
 #include "lbm_kernels.h"
 #include "lbm_tile2d.h"
@@ -150,8 +153,13 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
   }
 }
 
+// Two 8-wave workgroups per compute unit need at most 128 VGPRs per lane;
+// asking for 4 waves per SIMD keeps the 16-bit storage instantiations there
+// (their codec constants otherwise push them to 3 waves per SIMD, one
+// workgroup per compute unit).  FP64 cannot reach it and stays at 2.
 template <class Store, class Real, bool NS, bool HEAT, int MODE>
-__global__ __launch_bounds__(NT2) void k_step2d(const KArgs<Real, Store> a) {
+__global__ __launch_bounds__(NT2) __attribute__((amdgpu_waves_per_eu(4))) void k_step2d(
+    const KArgs<Real, Store> a) {
   __shared__ Real sphi[R1Y][R1X];
   __shared__ Real sux[R2Y][R2X];
   __shared__ Real suy[R2Y][R2X];

@@ -77,19 +77,20 @@ __device__ inline void store_family(const KArgs<Real, Store>& a, int off, int fa
 }
 
 // Directional-derivative gradient and Laplacian (Eqs. DerivDirec_Grad, Grad,
-// DerivDirect_Laplacian, Laplacian) of an LDS field at (ry, rx).  The sums
-// run over the D2Q9 directions; a direction and its opposite contribute the
-// same term, so each pair is taken once with weight 2 (exact rewrite).
-template <class Real, int RX>
-__device__ inline void stencil2d(const Real (*s)[RX], int ry, int rx, Real* g, Real& lap) {
-  const Real c = s[ry][rx];
+// DerivDirect_Laplacian, Laplacian) of a field read through at(dy, dx), the
+// value at offset (dx, dy) from the centre.  The sums run over the D2Q9
+// directions; a direction and its opposite contribute the same term, so each
+// pair is taken once with weight 2 (exact rewrite).
+template <class Real, class At>
+__device__ __forceinline__ void stencil2d_at(const At& at, Real* g, Real& lap) {
+  const Real c = at(0, 0);
   Real gx = 0, gy = 0, l = 0, wsum = 0;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     if (i > D2Q9::opp(i)) continue;
     const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
     const Real w = (Real)D2Q9::w(i);
-    const Real p = s[ry + cy][rx + cx], m = s[ry - cy][rx - cx];
+    const Real p = at(cy, cx), m = at(-cy, -cx);
     if (cx) gx += w * (Real)cx * (p - m);
     if (cy) gy += w * (Real)cy * (p - m);
     l += w * (p + m);
@@ -101,23 +102,35 @@ __device__ inline void stencil2d(const Real (*s)[RX], int ry, int rx, Real* g, R
   lap = (l - (Real)2 * wsum * c) * (Real)6;
 }
 
-// div(u phi): the Eq. Grad stencil applied to u_a phi, a-th component, summed.
-template <class Real>
-__device__ inline Real divergence2d(const Real (*sphi)[R1X], const Real (*sux)[R2X],
-                                    const Real (*suy)[R2X], int ry2, int rx2) {
+template <class Real, int RX>
+__device__ __forceinline__ void stencil2d(const Real (*s)[RX], int ry, int rx, Real* g, Real& lap) {
+  stencil2d_at<Real>([&](int dy, int dx) { return s[ry + dy][rx + dx]; }, g, lap);
+}
+
+// div(u phi): the Eq. Grad stencil applied to u_a phi, a-th component,
+// summed; phi(dy, dx), ux(dy, dx), uy(dy, dx) read at offsets from the node.
+template <class Real, class P, class UX, class UY>
+__device__ __forceinline__ Real divergence2d_at(const P& phi, const UX& ux, const UY& uy) {
   Real d = 0;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     if (i > D2Q9::opp(i)) continue;
     const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
     const Real w = (Real)D2Q9::w(i);
-    const Real pp = sphi[ry2 + 1 + cy][rx2 + 1 + cx], pm = sphi[ry2 + 1 - cy][rx2 + 1 - cx];
-    if (cx != 0)
-      d += w * (Real)cx * (sux[ry2 + cy][rx2 + cx] * pp - sux[ry2 - cy][rx2 - cx] * pm);
-    if (cy != 0)
-      d += w * (Real)cy * (suy[ry2 + cy][rx2 + cx] * pp - suy[ry2 - cy][rx2 - cx] * pm);
+    const Real pp = phi(cy, cx), pm = phi(-cy, -cx);
+    if (cx != 0) d += w * (Real)cx * (ux(cy, cx) * pp - ux(-cy, -cx) * pm);
+    if (cy != 0) d += w * (Real)cy * (uy(cy, cx) * pp - uy(-cy, -cx) * pm);
   }
   return d * (Real)3;
+}
+
+template <class Real>
+__device__ __forceinline__ Real divergence2d(const Real (*sphi)[R1X], const Real (*sux)[R2X],
+                                             const Real (*suy)[R2X], int ry2, int rx2) {
+  return divergence2d_at<Real>(
+      [&](int dy, int dx) { return sphi[ry2 + 1 + dy][rx2 + 1 + dx]; },
+      [&](int dy, int dx) { return sux[ry2 + dy][rx2 + dx]; },
+      [&](int dy, int dx) { return suy[ry2 + dy][rx2 + dx]; });
 }
 
 // Map a region coordinate to the domain: wraps periodic axes; returns false

@@ -91,3 +91,11 @@ def test_null_arguments(lib):
     p = lbm.make_params(I.film2d_params(16, 16), "f32")
     assert lib.lbm_create(C.byref(p), None, 0, None, C.byref(out)) == lbm.LBM_E_INVAL
     assert out.value is None
+
+
+def test_walled_axis_needs_two_nodes(lib):
+    assert _status(I.film2d_params(16, 1))[0] == lbm.LBM_E_INVAL   # y walls, one row
+    assert b"walled axis" in lib.lbm_last_error()
+    assert _status(I.film2d_params(16, 2))[0] == lbm.LBM_OK
+    prm = I.film2d_params(1, 8)   # x periodic: one column is allowed
+    assert _status(prm)[0] == lbm.LBM_OK
