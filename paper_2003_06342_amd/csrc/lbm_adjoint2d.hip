@@ -51,17 +51,18 @@ __device__ inline Real lfield(const KArgs<Real, Store>& a, const Real* f, int x,
 // ---------------------------------------------------------------------------
 // K_A: local adjoint
 // ---------------------------------------------------------------------------
-template <class Real>
-__global__ __launch_bounds__(NT2) void k_adj_local2d(const KArgs<Real, Real> a, const AdjArgs<Real> b) {
-  __shared__ Real sphi[R1Y][R1X];
-  __shared__ Real sux[R2Y][R2X];
-  __shared__ Real suy[R2Y][R2X];
+template <class Real, int TY>
+__global__ __launch_bounds__(Tile2<TY>::NT) void k_adj_local2d(const KArgs<Real, Real> a,
+                                                              const AdjArgs<Real> b) {
+  __shared__ Real sphi[Tile2<TY>::R1Y][R1X];
+  __shared__ Real sux[Tile2<TY>::R2Y][R2X];
+  __shared__ Real suy[Tile2<TY>::R2Y][R2X];
   const int tiles_x = (a.nx + TX2 - 1) / TX2;
   const int t = blockIdx.x;
-  const int x0 = (t % tiles_x) * TX2, y0 = (t / tiles_x) * TY2;
-  stage2d<Real, Real, true, true, false>(a, sphi, sux, suy, x0, y0);
+  const int x0 = (t % tiles_x) * TX2, y0 = (t / tiles_x) * TY;
+  stage2d<Real, Real, true, true, false, TY>(a, sphi, sux, suy, x0, y0);
   const int tid = threadIdx.x, lx = tid % TX2;
-  for (int r = tid / TX2; r < TY2; r += NT2 / TX2) {
+  for (int r = tid / TX2; r < TY; r += Tile2<TY>::NT / TX2) {
     const int x = x0 + lx, y = y0 + r;
     if (x >= a.nx || y >= a.ny) continue;
     const unsigned node = (unsigned)(y * a.px + x);
@@ -373,8 +374,12 @@ static dim3 node_grid(const KArgs<Real, Real>& a) {
 
 template <class Real>
 hipError_t launch_adj_step2d_t(const KArgs<Real, Real>& a, const AdjArgs<Real>& b, hipStream_t st) {
-  const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + TY2 - 1) / TY2);
-  hipLaunchKernelGGL(k_adj_local2d<Real>, dim3(tiles), dim3(NT2), 0, st, a, b);
+  const int ty = tile_rows2d(a.nx, a.ny);
+  const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + ty - 1) / ty);
+  if (ty == 64)
+    hipLaunchKernelGGL((k_adj_local2d<Real, 64>), dim3(tiles), dim3(Tile2<64>::NT), 0, st, a, b);
+  else
+    hipLaunchKernelGGL((k_adj_local2d<Real, 16>), dim3(tiles), dim3(Tile2<16>::NT), 0, st, a, b);
   hipLaunchKernelGGL(k_adj_u2d<Real>, node_grid(a), dim3(256), 0, st, a, b);
   hipLaunchKernelGGL(k_adj_phi2d<Real>, node_grid(a), dim3(256), 0, st, a, b, (Real*)nullptr);
   hipLaunchKernelGGL(k_adj_push2d<Real>, node_grid(a), dim3(256), 0, st, a, b);

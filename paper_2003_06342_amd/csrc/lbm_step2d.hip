@@ -25,18 +25,18 @@
 
 namespace lbm {
 
-template <class Store, class Real, bool NS, bool HEAT, int MODE, bool FAST>
+template <class Store, class Real, bool NS, bool HEAT, int MODE, bool FAST, int TY>
 __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*sphi)[R1X],
                                             Real (*sux)[R2X], Real (*suy)[R2X], int x0, int y0) {
   using C = Codec<Real, Store>;
   using Sc = typename ScalarOf<Store>::T;
   const int tid = threadIdx.x;
-  stage2d<Store, Real, NS, HEAT, FAST>(a, sphi, sux, suy, x0, y0);
+  stage2d<Store, Real, NS, HEAT, FAST, TY>(a, sphi, sux, suy, x0, y0);
 
   // ---- phase 3: the tile's nodes ------------------------------------------
   double acc_phi = 0, acc_T = 0, acc_phip = 0, acc_umax = 0, acc_bad = 0;
   const int lx = tid % TX2;
-  for (int r = tid / TX2; r < TY2; r += NT2 / TX2) {
+  for (int r = tid / TX2; r < TY; r += Tile2<TY>::NT / TX2) {
     const int x = x0 + lx, y = y0 + r;
     if (x >= a.nx || y >= a.ny) continue;
     const unsigned node = (unsigned)(y * a.px + x);
@@ -157,27 +157,27 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
 // asking for 4 waves per SIMD keeps the 16-bit storage instantiations there
 // (their codec constants otherwise push them to 3 waves per SIMD, one
 // workgroup per compute unit).  FP64 cannot reach it and stays at 2.
-template <class Store, class Real, bool NS, bool HEAT, int MODE>
-__global__ __launch_bounds__(NT2) __attribute__((amdgpu_waves_per_eu(4))) void k_step2d(
+template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY>
+__global__ __launch_bounds__(Tile2<TY>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_step2d(
     const KArgs<Real, Store> a) {
-  __shared__ Real sphi[R1Y][R1X];
-  __shared__ Real sux[R2Y][R2X];
-  __shared__ Real suy[R2Y][R2X];
+  __shared__ Real sphi[Tile2<TY>::R1Y][R1X];
+  __shared__ Real sux[Tile2<TY>::R2Y][R2X];
+  __shared__ Real suy[Tile2<TY>::R2Y][R2X];
   const int tiles_x = (a.nx + TX2 - 1) / TX2;
-  const int ntiles = tiles_x * ((a.ny + TY2 - 1) / TY2);
+  const int ntiles = tiles_x * ((a.ny + TY - 1) / TY);
   // XCD-aware order: hardware deals blocks to the 8 XCDs round-robin; give
   // each XCD a contiguous band of tiles so neighbouring tiles share an L2.
   int t = blockIdx.x;
   const int full = (ntiles / 8) * 8;
   if (t < full) t = (t % 8) * (full / 8) + t / 8;
-  const int x0 = (t % tiles_x) * TX2, y0 = (t / tiles_x) * TY2;
+  const int x0 = (t % tiles_x) * TX2, y0 = (t / tiles_x) * TY;
   // interior tile: every source node of the 2-halo region (3 nodes out)
   // lies inside the domain, so no wall link and no periodic wrap occurs
-  const bool interior = x0 >= 3 && x0 + TX2 + 3 <= a.nx && y0 >= 3 && y0 + TY2 + 3 <= a.ny;
+  const bool interior = x0 >= 3 && x0 + TX2 + 3 <= a.nx && y0 >= 3 && y0 + TY + 3 <= a.ny;
   if (interior)
-    step_tile2d<Store, Real, NS, HEAT, MODE, true>(a, sphi, sux, suy, x0, y0);
+    step_tile2d<Store, Real, NS, HEAT, MODE, true, TY>(a, sphi, sux, suy, x0, y0);
   else
-    step_tile2d<Store, Real, NS, HEAT, MODE, false>(a, sphi, sux, suy, x0, y0);
+    step_tile2d<Store, Real, NS, HEAT, MODE, false, TY>(a, sphi, sux, suy, x0, y0);
 }
 
 // Initialisation: populations = equilibrium - S/2 at the given fields with
@@ -338,21 +338,28 @@ __global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, cons
 template <class Store, class Real>
 static hipError_t launch_step2d_t(const KArgs<Real, Store>& a, int ns, int heat, int mode,
                                   hipStream_t st) {
-  const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + TY2 - 1) / TY2);
-  dim3 grid(tiles), block(NT2);
-#define LBM_L(NSV, HV, MV) \
-  hipLaunchKernelGGL((k_step2d<Store, Real, NSV, HV, MV>), grid, block, 0, st, a)
+  // MODE_MACRO always uses 64-row tiles: its per-block partials are sized by
+  // step2d_blocks
+  const int ty = mode == MODE_STEP ? tile_rows2d(a.nx, a.ny) : 64;
+  const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + ty - 1) / ty);
+#define LBM_L(NSV, HV, MV, TYV)                                                           \
+  hipLaunchKernelGGL((k_step2d<Store, Real, NSV, HV, MV, TYV>), dim3(tiles),              \
+                     dim3(Tile2<TYV>::NT), 0, st, a)
+#define LBM_L2(NSV, HV, MV)            \
+  if (ty == 64) LBM_L(NSV, HV, MV, 64); \
+  else LBM_L(NSV, HV, MV, 16)
   if (mode == MODE_STEP) {
-    if (ns && heat) LBM_L(true, true, MODE_STEP);
-    else if (ns) LBM_L(true, false, MODE_STEP);
-    else if (heat) LBM_L(false, true, MODE_STEP);
-    else LBM_L(false, false, MODE_STEP);
+    if (ns && heat) { LBM_L2(true, true, MODE_STEP); }
+    else if (ns) { LBM_L2(true, false, MODE_STEP); }
+    else if (heat) { LBM_L2(false, true, MODE_STEP); }
+    else { LBM_L2(false, false, MODE_STEP); }
   } else {
-    if (ns && heat) LBM_L(true, true, MODE_MACRO);
-    else if (ns) LBM_L(true, false, MODE_MACRO);
-    else if (heat) LBM_L(false, true, MODE_MACRO);
-    else LBM_L(false, false, MODE_MACRO);
+    if (ns && heat) LBM_L(true, true, MODE_MACRO, 64);
+    else if (ns) LBM_L(true, false, MODE_MACRO, 64);
+    else if (heat) LBM_L(false, true, MODE_MACRO, 64);
+    else LBM_L(false, false, MODE_MACRO, 64);
   }
+#undef LBM_L2
 #undef LBM_L
   return hipGetLastError();
 }

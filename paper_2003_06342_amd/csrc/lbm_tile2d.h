@@ -7,9 +7,21 @@
 
 namespace lbm {
 
+// Tiles are 64 columns wide (one wave64 per row) and TY rows high: 64 rows
+// with 512 lanes on large grids, 16 rows with 256 lanes where 64-row tiles
+// would leave compute units idle (fewer than two workgroups per CU).
 constexpr int TX2 = 64, TY2 = 64, NT2 = 512;
 constexpr int R1X = TX2 + 4, R1Y = TY2 + 4;   // phi region (halo 2)
 constexpr int R2X = TX2 + 2, R2Y = TY2 + 2;   // u region (halo 1)
+template <int TY>
+struct Tile2 {
+  static constexpr int NT = TY >= 64 ? 512 : 256;
+  static constexpr int R1Y = TY + 4, R2Y = TY + 2;
+};
+inline int tile_rows2d(int nx, int ny) {
+  const long long tiles64 = (long long)((nx + TX2 - 1) / TX2) * ((ny + 63) / 64);
+  return tiles64 >= 512 ? 64 : 16;
+}
 
 // Pull the Q populations of family FAM (0 f, 1 g, 2 s) arriving at node
 // (x, y).  A link whose source lies beyond a wall reflects at the node:
@@ -146,12 +158,12 @@ __device__ inline int mirror(int g, int n) { return g < 0 ? -1 - g : 2 * n - 1 -
 
 // Stage phi on the tile + 2-halo and (NS && HEAT) u on the tile + 1-halo in
 // LDS, with wall ghosts (x ghosts first, then y ghosts, so corners compose).
-template <class Store, class Real, bool NS, bool HEAT, bool FAST>
+template <class Store, class Real, bool NS, bool HEAT, bool FAST, int TY = TY2>
 __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi)[R1X],
                                         Real (*sux)[R2X], Real (*suy)[R2X], int x0, int y0) {
   const int tid = threadIdx.x;
   // ---- phase 1: phi on the tile + 2-halo --------------------------------
-  for (int k = tid; k < R1X * R1Y; k += NT2) {
+  for (int k = tid; k < R1X * Tile2<TY>::R1Y; k += Tile2<TY>::NT) {
     const int ry = k / R1X, rx = k - ry * R1X;
     int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
     Real v = 0;
@@ -167,7 +179,7 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
   }
   __syncthreads();
   if (!FAST && a.wall[0]) {   // x ghosts first, then y ghosts (corners compose)
-    for (int k = tid; k < R1X * R1Y; k += NT2) {
+    for (int k = tid; k < R1X * Tile2<TY>::R1Y; k += Tile2<TY>::NT) {
       const int ry = k / R1X, rx = k - ry * R1X;
       const int gx = x0 - 2 + rx;
       if (gx < 0 || gx >= a.nx) {
@@ -178,12 +190,12 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
     __syncthreads();
   }
   if (!FAST && a.wall[1]) {
-    for (int k = tid; k < R1X * R1Y; k += NT2) {
+    for (int k = tid; k < R1X * Tile2<TY>::R1Y; k += Tile2<TY>::NT) {
       const int ry = k / R1X, rx = k - ry * R1X;
       const int gy = y0 - 2 + ry;
       if (gy < 0 || gy >= a.ny) {
         const int my = mirror(gy, a.ny) - (y0 - 2);
-        if (my >= 0 && my < R1Y) sphi[ry][rx] = (Real)2 * a.phi_w[1][gy < 0 ? 0 : 1] - sphi[my][rx];
+        if (my >= 0 && my < Tile2<TY>::R1Y) sphi[ry][rx] = (Real)2 * a.phi_w[1][gy < 0 ? 0 : 1] - sphi[my][rx];
       }
     }
     __syncthreads();
@@ -191,7 +203,7 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
 
   // ---- phase 2: u on the tile + 1-halo -----------------------------------
   if constexpr (NS && HEAT) {
-    for (int k = tid; k < R2X * R2Y; k += NT2) {
+    for (int k = tid; k < R2X * Tile2<TY>::R2Y; k += Tile2<TY>::NT) {
       const int ry = k / R2X, rx = k - ry * R2X;
       int gx = x0 - 1 + rx, gy = y0 - 1 + ry;
       Real ux = 0, uy = 0;
@@ -216,7 +228,7 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
     }
     __syncthreads();
     if (!FAST && a.wall[0]) {
-      for (int k = tid; k < R2X * R2Y; k += NT2) {
+      for (int k = tid; k < R2X * Tile2<TY>::R2Y; k += Tile2<TY>::NT) {
         const int ry = k / R2X, rx = k - ry * R2X;
         const int gx = x0 - 1 + rx;
         if (gx < 0 || gx >= a.nx) {
@@ -230,12 +242,12 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
       __syncthreads();
     }
     if (!FAST && a.wall[1]) {
-      for (int k = tid; k < R2X * R2Y; k += NT2) {
+      for (int k = tid; k < R2X * Tile2<TY>::R2Y; k += Tile2<TY>::NT) {
         const int ry = k / R2X, rx = k - ry * R2X;
         const int gy = y0 - 1 + ry;
         if (gy < 0 || gy >= a.ny) {
           const int my = mirror(gy, a.ny) - (y0 - 1);
-          if (my >= 0 && my < R2Y) {
+          if (my >= 0 && my < Tile2<TY>::R2Y) {
             sux[ry][rx] = -sux[my][rx];
             suy[ry][rx] = -suy[my][rx];
           }

@@ -171,3 +171,22 @@ def test_film_f32_1000_steps():
     FP32 floor of the same algorithm (factor 5)."""
     prm, phi0, T0 = film_case(192, 128, 24.0, 3.0)
     _check_f32("film_f32_1000", prm, phi0, T0, 1000, factor=5.0)
+
+
+def test_film_full_size_1024x2048_bench_configuration():
+    """The benchmark workload itself (1024 x 2048 film, seed 0, h = 64 +
+    4 cos + noise), in the launch configuration bench.py times (64-row
+    tiles, which only grids of at least 512 such tiles use): 4 steps in FP64
+    storage against the oracle within 1e-10, and FP32 storage within 1e-5
+    (four steps are far from the FP32 rounding floor)."""
+    need_gpu()
+    prm, phi0, T0 = film_case(1024, 2048, 64.0, 4.0)
+    nsteps = 4
+    say(f"[parity] full size 1024x2048: oracle {nsteps} steps")
+    ref = oracle_run(prm, phi0, T0, nsteps)
+    for storage, tol in (("f64", 1e-10), ("f32", 1e-5)):
+        gpu = gpu_run(prm, phi0, T0, nsteps, storage)
+        errs = compare(gpu, ref)
+        say(f"[parity] full size {storage}: errors {errs}")
+        for k in ("phi", "T", "umag", "p"):
+            assert errs[k] <= tol, (storage, k, errs)
