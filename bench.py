@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -111,9 +112,15 @@ def adjoint_ratio(nx=512, ny=512, nsteps=200):
     torch.cuda.synchronize()
     t_bwd = (time.perf_counter() - t0) / nsteps
     sim.close()
+    # sqrt(T) checkpointing: segments of K = ceil(sqrt(N)) steps; the reverse
+    # sweep recomputes K - 1 steps per segment (taped forward steps)
+    K = math.ceil(math.sqrt(nsteps))
+    nseg = (nsteps + K - 1) // K
+    t_adj = t_bwd - (nsteps - nseg) * t_tape / nsteps
     return dict(grid=f"{nx}x{ny}", steps=nsteps, fwd_ms=round(1e3 * t_fwd, 4),
                 taped_fwd_ms=round(1e3 * t_tape, 4), bwd_ms_per_step=round(1e3 * t_bwd, 4),
-                ratio_with_recompute=round(t_bwd / t_fwd, 3))
+                ratio_with_recompute=round(t_bwd / t_fwd, 3),
+                ratio_adjoint_kernels=round(t_adj / t_fwd, 3))
 
 
 def cpu_baseline(prm, fields, budget_s=20.0):

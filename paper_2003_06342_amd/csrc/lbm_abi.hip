@@ -619,6 +619,7 @@ lbm_status backward_t(lbm_ctx* c, const void* gphi, int32_t gdt, void* ws, void*
       KArgs<Real, Real> a = make_args_blobs<Real, Real>(c, seg + (size_t)k * ss, nullptr);
       e = launch_adj_step2d(a, b, c->stream);
       if (e != hipSuccess) return hip_check(e, "adjoint step");
+      std::swap(b.lA, b.lP);   // the step left lambda_A of state k in lP
     }
   }
   {  // initial condition (segment 0's first state is X^0)

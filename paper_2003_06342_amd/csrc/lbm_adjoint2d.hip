@@ -12,9 +12,12 @@
 //   K_C  phi:     transposed gradient (antisymmetric) and Laplacian
 //                 (symmetric) stencils with Dirichlet ghosts; phi = sum g +
 //                 q_prev/2 distributes lambda_phi to the pulled g and q_prev.
-//   K_D  push:    transpose of the pull gather (each slot of A is read by
-//                 exactly one pull); anti-bounce-back links of s add
-//                 2 w_i lambda to the wall-temperature gradient.
+// The transpose of the pull gather is folded into these kernels: each slot
+// of A is read by exactly one pull, so the adjoint of a pulled population is
+// stored (K_A) or accumulated (K_B for f, K_C for g) straight into the slot
+// it was read from, in a second buffer that becomes lambda_A of the earlier
+// state; anti-bounce-back links of s add 2 w_i lambda to the wall-temperature
+// gradient (K_A).  K_D (push) remains for the seed only.
 // Supports at most one walled axis (ghost corners are not differentiated).
 #include "lbm_adjoint.h"
 #include "lbm_adjargs.h"
@@ -29,14 +32,25 @@ __device__ inline Real ldp(const Real* p, long long slab, int plane, unsigned no
   return p[(size_t)plane * (size_t)slab + node];
 }
 
+// Periodic wrap of a coordinate at most two nodes outside [0, n) (the
+// stencils here reach x +- 1 around ghost positions x = -1 and x = n), by
+// compares instead of an integer division.
+__device__ __forceinline__ int wrap2(int s, int n) {
+  s += s < 0 ? n : 0;
+  s += s < 0 ? n : 0;
+  s -= s >= n ? n : 0;
+  s -= s >= n ? n : 0;
+  return s;
+}
+
 // Global-memory phi with Dirichlet ghosts (one walled axis at most).
 template <class Real, class Store>
 __device__ inline Real phi_g(const KArgs<Real, Store>& a, const Real* fphi, int x, int y) {
   if (a.wall[1] && (y < 0 || y >= a.ny))
-    return (Real)2 * a.phi_w[1][y < 0 ? 0 : 1] - fphi[(unsigned)(mirror(y, a.ny) * a.px + wrapmod(x, a.nx))];
+    return (Real)2 * a.phi_w[1][y < 0 ? 0 : 1] - fphi[(unsigned)(mirror(y, a.ny) * a.px + wrap2(x, a.nx))];
   if (a.wall[0] && (x < 0 || x >= a.nx))
-    return (Real)2 * a.phi_w[0][x < 0 ? 0 : 1] - fphi[(unsigned)(wrapmod(y, a.ny) * a.px + mirror(x, a.nx))];
-  return fphi[(unsigned)(wrapmod(y, a.ny) * a.px + wrapmod(x, a.nx))];
+    return (Real)2 * a.phi_w[0][x < 0 ? 0 : 1] - fphi[(unsigned)(wrap2(y, a.ny) * a.px + mirror(x, a.nx))];
+  return fphi[(unsigned)(wrap2(y, a.ny) * a.px + wrap2(x, a.nx))];
 }
 
 // A node-valued adjoint field read at (x, y): 0 beyond a wall (no stencil is
@@ -45,14 +59,41 @@ template <class Real, class Store>
 __device__ inline Real lfield(const KArgs<Real, Store>& a, const Real* f, int x, int y) {
   if (a.wall[1] && (y < 0 || y >= a.ny)) return 0;
   if (a.wall[0] && (x < 0 || x >= a.nx)) return 0;
-  return f[(unsigned)(wrapmod(y, a.ny) * a.px + wrapmod(x, a.nx))];
+  return f[(unsigned)(wrap2(y, a.ny) * a.px + wrap2(x, a.nx))];
+}
+
+// Slot of A read by the pull of population i of family fam at node (x, y),
+// with the sign of that read (-1 on the anti-bounce-back links of g and s)
+// and, for a link reflected at a wall, the wall (axis, side); wax = -1 else.
+template <class Real, class Store>
+__device__ inline size_t pull_slot(const KArgs<Real, Store>& a, int fam, int i, int x, int y,
+                                   Real& sign, int& wax, int& wside) {
+  const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+  int sx = x - cx, sy = y - cy;
+  const bool oy = cy != 0 && a.wall[1] && (sy < 0 || sy >= a.ny);
+  const bool ox = cx != 0 && !oy && a.wall[0] && (sx < 0 || sx >= a.nx);
+  wax = -1;
+  wside = 0;
+  if (oy || ox) {
+    sign = fam == 0 ? (Real)1 : (Real)-1;
+    wax = oy ? 1 : 0;
+    wside = oy ? (sy < 0 ? 0 : 1) : (sx < 0 ? 0 : 1);
+    return (size_t)(fam * 9 + D2Q9::opp(i)) * (size_t)a.slab + (unsigned)(y * a.px + x);
+  }
+  if (!a.wall[0]) sx = wrap1(sx, a.nx);
+  if (!a.wall[1]) sy = wrap1(sy, a.ny);
+  sign = 1;
+  return (size_t)(fam * 9 + i) * (size_t)a.slab + (unsigned)(sy * a.px + sx);
 }
 
 // ---------------------------------------------------------------------------
 // K_A: local adjoint
 // ---------------------------------------------------------------------------
+// node_adj keeps the node's inputs, output adjoints and input adjoints live
+// together (about 256 VGPRs); two waves per SIMD is the most it reaches
+// without heavy spilling.
 template <class Real, int TY>
-__global__ __launch_bounds__(Tile2<TY>::NT) void k_adj_local2d(const KArgs<Real, Real> a,
+__global__ __launch_bounds__(Tile2<TY>::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_local2d(const KArgs<Real, Real> a,
                                                               const AdjArgs<Real> b) {
   __shared__ Real sphi[Tile2<TY>::R1Y][R1X];
   __shared__ Real sux[Tile2<TY>::R2Y][R2X];
@@ -88,11 +129,23 @@ __global__ __launch_bounds__(Tile2<TY>::NT) void k_adj_local2d(const KArgs<Real,
     lo.q = b.lqp[node];
     NodeAdjIn<Real> li;
     adj::node_adj(b.nc, in, lo, li);
-    for (int i = 0; i < 9; ++i) {
-      b.lP[(size_t)i * a.slab + node] = li.Pf[i];
-      b.lP[(size_t)(9 + i) * a.slab + node] = li.Pg[i];
-      b.lP[(size_t)(18 + i) * a.slab + node] = li.Ps[i];
-    }
+    // adjoints of the pulled populations, stored at the slots they were read
+    // from (transpose of the pull)
+    Real tw[2][2] = {{0, 0}, {0, 0}};
+    const Real* lsets[3] = {li.Pf, li.Pg, li.Ps};
+#pragma unroll
+    for (int fam = 0; fam < 3; ++fam)
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        Real sg;
+        int wax, wsd;
+        const size_t slot = pull_slot(a, fam, i, x, y, sg, wax, wsd);
+        b.lP[slot] = sg * lsets[fam][i];
+        if (fam == 2 && wax >= 0) tw[wax][wsd] += (Real)2 * (Real)D2Q9::w(i) * lsets[fam][i];
+      }
+    for (int ax = 0; ax < 2; ++ax)
+      for (int sd = 0; sd < 2; ++sd)
+        if (b.lTw[ax][sd] && tw[ax][sd] != (Real)0) b.lTw[ax][sd][ax == 1 ? x : y] += tw[ax][sd];
     // phi_prev of the next state is this step's phi
     b.lloc[(size_t)LL_PHI * a.slab + node] = li.phi + b.lphip[node];
     b.lloc[(size_t)LL_GX * a.slab + node] = li.gphi[0];
@@ -183,7 +236,12 @@ __global__ __launch_bounds__(256) void k_adj_u2d(const KArgs<Real, Real> a, cons
   Real lPf[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   Real l_phi_u, l_g[2], l_lap;
   adj::u_adj(b.nc, Pf, phi, g, lap, lu, lPf, l_phi_u, l_g, l_lap);
-  for (int i = 0; i < 9; ++i) b.lP[(size_t)i * a.slab + node] += lPf[i];
+  for (int i = 0; i < 9; ++i) {
+    Real sg;
+    int wax, wsd;
+    const size_t slot = pull_slot(a, 0, i, x, y, sg, wax, wsd);
+    b.lP[slot] += sg * lPf[i];
+  }
   b.lloc[(size_t)LL_PHI * a.slab + node] += lphi + l_phi_u;
   b.lloc[(size_t)LL_GX * a.slab + node] += l_g[0];
   b.lloc[(size_t)LL_GY * a.slab + node] += l_g[1];
@@ -238,7 +296,12 @@ __global__ __launch_bounds__(256) void k_adj_phi2d(const KArgs<Real, Real> a, co
     lphi_out[(unsigned)(y * a.nx + x)] = lphi;
     return;
   }
-  for (int i = 0; i < 9; ++i) b.lP[(size_t)(9 + i) * a.slab + node] += lphi;
+  for (int i = 0; i < 9; ++i) {
+    Real sg;
+    int wax, wsd;
+    const size_t slot = pull_slot(a, 1, i, x, y, sg, wax, wsd);
+    b.lP[slot] += sg * lphi;
+  }
   b.lqp[node] = (Real)0.5 * lphi;
 }
 
@@ -382,7 +445,6 @@ hipError_t launch_adj_step2d_t(const KArgs<Real, Real>& a, const AdjArgs<Real>& 
     hipLaunchKernelGGL((k_adj_local2d<Real, 16>), dim3(tiles), dim3(Tile2<16>::NT), 0, st, a, b);
   hipLaunchKernelGGL(k_adj_u2d<Real>, node_grid(a), dim3(256), 0, st, a, b);
   hipLaunchKernelGGL(k_adj_phi2d<Real>, node_grid(a), dim3(256), 0, st, a, b, (Real*)nullptr);
-  hipLaunchKernelGGL(k_adj_push2d<Real>, node_grid(a), dim3(256), 0, st, a, b);
   return hipGetLastError();
 }
 
