@@ -37,12 +37,16 @@ def bytes_per_node(dim: int, q_total: int, storage: str) -> int:
     return q_total * pe * 2 + 2 * se * 2
 
 
+# sources of the dominant kernel (k_step2d); HBM counters recorded under
+# profiles/ are used only while these are unchanged
+STEP2D_SOURCES = ("lbm_device.h", "lbm_kernels.h", "lbm_tile2d.h", "lbm_step2d.hip")
+
+
 def kernel_sources_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2003_06342_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, name), "rb").read())
+    for name in STEP2D_SOURCES:
+        h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -162,6 +166,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--only", choices=["film3d256", "adjoint"],
+                    help="run one secondary measurement alone (for profiling) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build targets one GPU; --gpus {args.gpus} is not supported "
@@ -170,6 +176,15 @@ def main():
     import torch
     from paper_2003_06342_amd import inputs as I
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.only == "film3d256":
+        p3 = I.film3d_params(256)
+        f3 = I.film3d_fields(p3, seed=1, h0=32.0, amp=3.0)
+        r = time_variant(p3, f3, "f32", args.steps, args.warmup)
+        print(json.dumps({"film3d_256^3_f32": r}), flush=True)
+        return
+    if args.only == "adjoint":
+        print(json.dumps({"adjoint_512x512_f32": adjoint_ratio()}), flush=True)
+        return
 
     nx, ny = 1024, 2048
     prm = I.film2d_params(nx, ny)

@@ -138,3 +138,25 @@ def test_adjoint_vs_central_fd_config4_size(n, bar):
         e = rel_l2(ads[kind], fds[kind])
         say(f"[adjoint] n={n} {kind}: relative L2 over 16 directions {e:.2e}")
         assert e <= bar, (kind, e)
+
+
+def test_autograd_function_matches_oracle():
+    """The torch.autograd.Function bridge (LBMRun) on CUDA tensors: the
+    gradients reaching phi0 and T_w through loss.backward() equal the FP64
+    oracle's reverse pass."""
+    need_gpu()
+    from paper_2003_06342_amd.autograd import LBMRun
+    prm, phi0, T0, Tw = film(24, 20, 6.0, 1.5, g=2e-4)
+    n = 12
+    phi_o = torch.tensor(phi0, dtype=F64, requires_grad=True)
+    tw_o = torch.tensor(Tw, dtype=F64, requires_grad=True)
+    M = Model(prm, T_wall_faces={(1, 0): tw_o.reshape(1, 1, -1)})
+    (M.fields(M.run(M.init(phi_o, T0), n))["phi"] ** 2).mean().backward()
+    phi_g = torch.tensor(phi0, dtype=F64, device="cuda", requires_grad=True)
+    tw_g = torch.tensor(Tw, dtype=F64, device="cuda", requires_grad=True)
+    phiN = LBMRun.apply(phi_g, tw_g, prm, T0, n, "f64")
+    (phiN ** 2).mean().backward()
+    e_phi = rel_l2(phi_g.grad.cpu().numpy(), phi_o.grad.numpy())
+    e_tw = rel_l2(tw_g.grad.cpu().numpy(), tw_o.grad.numpy())
+    say(f"[adjoint] autograd.Function: dphi0 {e_phi:.2e} dTw {e_tw:.2e}")
+    assert e_phi < 1e-9 and e_tw < 1e-9
