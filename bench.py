@@ -31,10 +31,12 @@ METRIC = "MLUPS + % HBM roofline, FP32 & FP16-store vs FP64 oracle error; adjoin
 
 def bytes_per_node(dim: int, q_total: int, storage: str) -> int:
     """Algorithmic bytes per node update: every population read once and
-    written once, plus phi_prev and q_prev read and written."""
+    written once, plus phi_prev and q_prev (and, for 16-bit storage, the
+    per-node temperature reference of the s family) read and written."""
     pe = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}[storage]
     se = 8 if storage == "f64" else 4
-    return q_total * pe * 2 + 2 * se * 2
+    nsc = 3 if pe == 2 else 2
+    return q_total * pe * 2 + nsc * se * 2
 
 
 # sources of the dominant kernel (k_step2d); HBM counters recorded under

@@ -56,8 +56,11 @@ typedef int32_t lbm_status;
 enum { LBM_D2Q9 = 9, LBM_D3Q7 = 7, LBM_D3Q19 = 19 };
 
 /* Population storage.  F16_DEV / BF16_DEV store each population as the
- * 16-bit float (value - w_i * ref) * 2^k with a per-family reference and
- * power-of-two scale; arithmetic is FP32.  Lagged scalars stay FP32. */
+ * 16-bit float (value - w_i * ref) * 2^k with a power-of-two scale;
+ * arithmetic is FP32.  ref is a per-family constant for f and g.  For the
+ * temperature family s it is per node: T_ref(x), the temperature of the node
+ * x that stored the population, kept as one more FP32 plane of the state.
+ * Lagged scalars stay FP32. */
 enum { LBM_ST_F64 = 0, LBM_ST_F32 = 1, LBM_ST_F16_DEV = 2, LBM_ST_BF16_DEV = 3 };
 
 /* Per-axis boundary: periodic, or half-way walls on both faces.  A wall is
@@ -153,8 +156,9 @@ lbm_status lbm_get_fields(lbm_ctx* ctx, uint32_t mask, void* dev_out, int32_t dt
  * LBM_E_UNSTABLE if the count is non-zero. */
 lbm_status lbm_diagnostics(lbm_ctx* ctx, double out[5]);
 
-/* Checkpoint / resume: the raw state (populations, lagged phi and q) as an
- * opaque byte blob of lbm_state_size bytes, copied device-to-device. */
+/* Checkpoint / resume: the raw state (populations, lagged phi and q, and
+ * T_ref for 16-bit storage) as an opaque byte blob of lbm_state_size bytes,
+ * copied device-to-device. */
 lbm_status lbm_state_size(const lbm_ctx* ctx, size_t* bytes);
 lbm_status lbm_get_state(lbm_ctx* ctx, void* dev_out, size_t bytes);
 lbm_status lbm_set_state(lbm_ctx* ctx, const void* dev_in, size_t bytes);

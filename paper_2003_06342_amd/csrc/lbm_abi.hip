@@ -47,6 +47,7 @@ struct Layout {
   long long slab;
   size_t elem, sc_elem, real_elem;
   size_t pops, scal, faces[3][2], partials;
+  int nsc;   // scalar planes per state: phi_prev, q_prev (+ T_ref for 16-bit storage)
   size_t total;
   int nblocks;
 };
@@ -61,6 +62,7 @@ struct lbm_ctx {
   void* pops[2];
   void* phip[2];
   void* qp[2];
+  void* tref[2];   // 16-bit storage: per-node reference of the s family
   void* tw[3][2];
   double* partials;
   double* red;
@@ -138,7 +140,9 @@ Layout layout(const lbm_params* p) {
   L.real_elem = p->storage == LBM_ST_F64 ? 8 : 4;
   L.pops = align256((size_t)L.Qtot * L.slab * L.elem);
   L.scal = align256((size_t)L.slab * L.sc_elem);
-  size_t tot = 2 * L.pops + 4 * L.scal;
+  const bool st16 = p->storage == LBM_ST_F16_DEV || p->storage == LBM_ST_BF16_DEV;
+  L.nsc = (st16 && heat) ? 3 : 2;
+  size_t tot = 2 * L.pops + 2 * (size_t)L.nsc * L.scal;
   const int n[3] = {p->nx, p->ny, p->nz};
   for (int a = 0; a < 3; ++a)
     for (int s = 0; s < 2; ++s) {
@@ -214,11 +218,14 @@ KArgs<Real, Store> make_args(const lbm_ctx* c) {
   a.A_qp = (const typename KArgs<Real, Store>::Sc*)c->qp[cur];
   a.B_phip = (typename KArgs<Real, Store>::Sc*)c->phip[1 - cur];
   a.B_qp = (typename KArgs<Real, Store>::Sc*)c->qp[1 - cur];
+  a.A_Tref = (const typename KArgs<Real, Store>::Sc*)c->tref[cur];
+  a.B_Tref = (typename KArgs<Real, Store>::Sc*)c->tref[1 - cur];
   return a;
 }
 
 // Kernel arguments reading state blob `in` and writing state blob `out`
-// (blob layout: populations | phi_prev | q_prev, each 256-byte aligned).
+// (blob layout: populations | phi_prev | q_prev [| T_ref], each 256-byte
+// aligned).
 template <class Real, class Store>
 KArgs<Real, Store> make_args_blobs(const lbm_ctx* c, const char* in, char* out) {
   KArgs<Real, Store> a = make_args<Real, Store>(c);
@@ -229,6 +236,8 @@ KArgs<Real, Store> make_args_blobs(const lbm_ctx* c, const char* in, char* out) 
   a.B = (Store*)out;
   a.B_phip = (Sc*)(out ? out + c->L.pops : nullptr);
   a.B_qp = (Sc*)(out ? out + c->L.pops + c->L.scal : nullptr);
+  a.A_Tref = c->L.nsc == 3 ? (const Sc*)(in + c->L.pops + 2 * c->L.scal) : nullptr;
+  a.B_Tref = (c->L.nsc == 3 && out) ? (Sc*)(out + c->L.pops + 2 * c->L.scal) : nullptr;
   return a;
 }
 
@@ -325,6 +334,11 @@ lbm_status lbm_create(const lbm_params* prm, void* ws, size_t bytes, void* strea
   c->qp[0] = p;    p += L.scal;
   c->phip[1] = p;  p += L.scal;
   c->qp[1] = p;    p += L.scal;
+  c->tref[0] = c->tref[1] = nullptr;
+  if (L.nsc == 3) {
+    c->tref[0] = p;  p += L.scal;
+    c->tref[1] = p;  p += L.scal;
+  }
   for (int a = 0; a < 3; ++a)
     for (int sd = 0; sd < 2; ++sd) {
       c->tw[a][sd] = L.faces[a][sd] ? (void*)p : nullptr;
@@ -459,14 +473,15 @@ lbm_status lbm_diagnostics(lbm_ctx* c, double out[5]) {
 
 lbm_status lbm_state_size(const lbm_ctx* c, size_t* bytes) {
   if (!c || !bytes) return fail(LBM_E_INVAL, "NULL argument");
-  *bytes = c->L.pops + 2 * c->L.scal;
+  *bytes = c->L.pops + (size_t)c->L.nsc * c->L.scal;
   return LBM_OK;
 }
 
 lbm_status lbm_get_state(lbm_ctx* c, void* out, size_t bytes) {
   if (!c || !out) return fail(LBM_E_INVAL, "NULL argument");
   if (!c->initialized) return fail(LBM_E_STATE, "no state yet");
-  if (bytes < c->L.pops + 2 * c->L.scal) return fail(LBM_E_NOMEM, "state buffer too small");
+  if (bytes < c->L.pops + (size_t)c->L.nsc * c->L.scal)
+    return fail(LBM_E_NOMEM, "state buffer too small");
   char* o = (char*)out;
   hipError_t e = hipMemcpyAsync(o, c->pops[c->cur], c->L.pops, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess)
@@ -474,12 +489,16 @@ lbm_status lbm_get_state(lbm_ctx* c, void* out, size_t bytes) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(o + c->L.pops + c->L.scal, c->qp[c->cur], c->L.scal, hipMemcpyDeviceToDevice,
                        c->stream);
+  if (e == hipSuccess && c->L.nsc == 3)
+    e = hipMemcpyAsync(o + c->L.pops + 2 * c->L.scal, c->tref[c->cur], c->L.scal,
+                       hipMemcpyDeviceToDevice, c->stream);
   return hip_check(e, "lbm_get_state");
 }
 
 lbm_status lbm_set_state(lbm_ctx* c, const void* in, size_t bytes) {
   if (!c || !in) return fail(LBM_E_INVAL, "NULL argument");
-  if (bytes < c->L.pops + 2 * c->L.scal) return fail(LBM_E_NOMEM, "state buffer too small");
+  if (bytes < c->L.pops + (size_t)c->L.nsc * c->L.scal)
+    return fail(LBM_E_NOMEM, "state buffer too small");
   const char* i = (const char*)in;
   hipError_t e = hipMemcpyAsync(c->pops[c->cur], i, c->L.pops, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess)
@@ -487,6 +506,9 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* in, size_t bytes) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->qp[c->cur], i + c->L.pops + c->L.scal, c->L.scal, hipMemcpyDeviceToDevice,
                        c->stream);
+  if (e == hipSuccess && c->L.nsc == 3)
+    e = hipMemcpyAsync(c->tref[c->cur], i + c->L.pops + 2 * c->L.scal, c->L.scal,
+                       hipMemcpyDeviceToDevice, c->stream);
   c->initialized = 1;
   c->step = 0;
   return hip_check(e, "lbm_set_state");
@@ -516,7 +538,7 @@ const char* lbm_version(void) { return "lbm-phasechange-gfx950 0.1"; }
 // ===========================================================================
 namespace {
 
-size_t state_bytes(const lbm_ctx* c) { return c->L.pops + 2 * c->L.scal; }
+size_t state_bytes(const lbm_ctx* c) { return c->L.pops + (size_t)c->L.nsc * c->L.scal; }
 
 lbm_status adjoint_supported(const lbm_ctx* c) {
   const lbm_params& p = c->prm;

@@ -10,6 +10,8 @@
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
 
 // ---------------------------------------------------------------------------
@@ -119,6 +121,13 @@ struct Codec<float, __hip_bfloat16> {
 template <class Store> struct ScalarOf { using T = float; };
 template <> struct ScalarOf<double> { using T = double; };
 
+// 16-bit storage keeps the s family as deviations from w_i T_ref(x), with
+// T_ref(x) the temperature of the node x that stored the population (one
+// scalar plane, written with the populations).  A slot (i, x) is always
+// encoded and decoded against T_ref(x), so pull and store agree.
+template <class Real, class Store>
+constexpr bool kNodeRef = !std::is_same<Real, Store>::value;
+
 // ---------------------------------------------------------------------------
 // Kernel argument block (passed by value).
 // ---------------------------------------------------------------------------
@@ -135,6 +144,10 @@ struct KArgs {
   Store* __restrict__ B;
   const Sc* __restrict__ A_phip;   // phi^{n-1}
   const Sc* __restrict__ A_qp;     // q^{n-1}
+  // 16-bit storage: per-node reference of the s family (the node's T when
+  // it stored its populations); null for FP32 / FP64
+  const Sc* __restrict__ A_Tref;
+  Sc* __restrict__ B_Tref;
   Sc* __restrict__ B_phip;
   Sc* __restrict__ B_qp;
   // per-node wall temperature on each walled face: [axis][side]

@@ -92,14 +92,18 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
       if constexpr (MODE == MODE_STEP) {
         const Real om = (Real)1 / (m.alpha * (Real)3 + (Real)0.5);
         collide_s<D2Q9>(a, s, m, om);
-        store_family<D2Q9>(a, a.off_s, 2, node, s);
+        // 16-bit storage: the s deviations are about this node's own T
+        const Real Tref = kNodeRef<Real, Store> ? (Real)(Sc)m.T : a.ref[2];
+        store_family<D2Q9>(a, a.off_s, 2, node, s, Tref);
+        if constexpr (kNodeRef<Real, Store>) st_plane(a.B_Tref, node, (Sc)m.T);
       }
     }
     if constexpr (MODE == MODE_STEP) {
       Real g[9];
       gather2d<D2Q9, 1, FAST>(a, x, y, g);
       collide_g<D2Q9>(a, g, m);
-      store_family<D2Q9>(a, a.off_g, 1, node, g);
+      store_family<D2Q9>(a, a.off_g, 1, node, g,
+                         kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1]);
     }
     const Real cs2 = (Real)(1.0 / 3.0);
     m.p = 0;
@@ -115,7 +119,7 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
         m.nu = viscosity(a, m.phi);
         const Real om = (Real)1 / (m.nu * (Real)3 + (Real)0.5);
         collide_f<D2Q9>(f, m, m.rho * cs2 * m.q * a.prod_fac, om);
-        store_family<D2Q9>(a, a.off_f, 0, node, f);
+        store_family<D2Q9>(a, a.off_f, 0, node, f, a.ref[0]);
       }
     }
     if constexpr (MODE == MODE_STEP) {
@@ -313,23 +317,34 @@ __global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, cons
         Vs = HEAT ? a.Tw[0][side][y] : (Real)0;
       }
       if (NS) a.B[(long long)(a.off_f + j) * a.slab + node] = C::enc(f[i], w * a.ref[0], a.scale[0]);
+      const Real gr = kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1];   // slot at this node
       a.B[(long long)(a.off_g + j) * a.slab + node] =
-          C::enc((Real)2 * w * Vg - g[i], w * a.ref[1], a.scale[1]);
-      if (HEAT)
+          C::enc((Real)2 * w * Vg - g[i], w * gr, a.scale[1]);
+      if (HEAT) {
+        const Real tr = kNodeRef<Real, Store> ? (Real)(Sc)m.T : a.ref[2];   // slot at this node
         a.B[(long long)(a.off_s + j) * a.slab + node] =
-            C::enc((Real)2 * w * Vs - s[i], w * a.ref[2], a.scale[2]);
+            C::enc((Real)2 * w * Vs - s[i], w * tr, a.scale[2]);
+      }
     } else {
       if (!a.wall[0]) sx = wrap1(sx, a.nx);
       if (!a.wall[1]) sy = wrap1(sy, a.ny);
       const long long node = (long long)sy * a.px + sx;
       if (NS) a.B[(long long)(a.off_f + i) * a.slab + node] = C::enc(f[i], w * a.ref[0], a.scale[0]);
-      a.B[(long long)(a.off_g + i) * a.slab + node] = C::enc(g[i], w * a.ref[1], a.scale[1]);
-      if (HEAT) a.B[(long long)(a.off_s + i) * a.slab + node] = C::enc(s[i], w * a.ref[2], a.scale[2]);
+      // the slot belongs to node (sx, sy): its reference is that node's phi0
+      const Real gr = kNodeRef<Real, Store> ? (Real)(Sc)ld(phi0, 0, sx, sy) : a.ref[1];
+      a.B[(long long)(a.off_g + i) * a.slab + node] = C::enc(g[i], w * gr, a.scale[1]);
+      if (HEAT) {
+        // the slot belongs to node (sx, sy): its reference is that node's T0
+        const Real tr = kNodeRef<Real, Store> ? (Real)(Sc)ld(T0, 0, sx, sy) : a.ref[2];
+        a.B[(long long)(a.off_s + i) * a.slab + node] = C::enc(s[i], w * tr, a.scale[2]);
+      }
     }
   }
   const long long node = (long long)y * a.px + x;
   a.B_phip[node] = (Sc)m.phi;
   a.B_qp[node] = (Sc)m.q;
+  if constexpr (kNodeRef<Real, Store>)
+    if (HEAT) a.B_Tref[node] = (Sc)m.T;
 }
 
 // ---------------------------------------------------------------------------

@@ -36,6 +36,9 @@ __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z
   const Store* __restrict__ base = a.A + (size_t)off * (size_t)a.slab;
   const int pz = a.px * a.ny;
   const unsigned node = (unsigned)(z * pz + y * a.px + x);
+  // 16-bit storage: g and s are deviations from w_i phi(src) and w_i T_ref(src)
+  constexpr bool NREF = FAM != 0 && kNodeRef<Real, Store>;
+  const typename KArgs<Real, Store>::Sc* __restrict__ rplane = FAM == 1 ? a.A_phip : a.A_Tref;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
     const int cx = Lat::cx(i), cy = Lat::cy(i), cz = Lat::cz(i);
@@ -44,7 +47,8 @@ __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z
     const bool oz = (cz != 0) && a.wall[2] && (sz < 0 || sz >= a.nz);
     if (oz) {
       const int j = Lat::opp(i);
-      Real r = C::dec((base + (size_t)j * (size_t)a.slab)[node], wref, inv);
+      const Real wr = NREF ? (Real)Lat::w(i) * (Real)rplane[node] : wref;
+      Real r = C::dec((base + (size_t)j * (size_t)a.slab)[node], wr, inv);
       if (FAM != 0) {
         const int side = sz < 0 ? 0 : 1;
         const Real V = FAM == 1 ? a.phi_w[2][side] : a.Tw[2][side][y * a.nx + x];
@@ -55,13 +59,16 @@ __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z
       if (cz != 0 && !a.wall[2]) sz = wrap1(sz, a.nz);
       if (XYIN) {
         const Store* __restrict__ p = base + (size_t)i * (size_t)a.slab;
-        v[i] = C::dec(p[(unsigned)((int)node - cx - cy * a.px + (sz - z) * pz)], wref, inv);
+        const unsigned src = (unsigned)((int)node - cx - cy * a.px + (sz - z) * pz);
+        const Real wr = NREF ? (Real)Lat::w(i) * (Real)rplane[src] : wref;
+        v[i] = C::dec(p[src], wr, inv);
       } else {
         int sx = x - cx, sy = y - cy;
         if (cx != 0) sx = wrap1(sx, a.nx);
         if (cy != 0) sy = wrap1(sy, a.ny);
-        v[i] = C::dec((base + (size_t)i * (size_t)a.slab)[(unsigned)(sz * pz + sy * a.px + sx)],
-                      wref, inv);
+        const unsigned src = (unsigned)(sz * pz + sy * a.px + sx);
+        const Real wr = NREF ? (Real)Lat::w(i) * (Real)rplane[src] : wref;
+        v[i] = C::dec((base + (size_t)i * (size_t)a.slab)[src], wr, inv);
       }
     }
   }
@@ -69,13 +76,12 @@ __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z
 
 template <class Lat, class Real, class Store>
 __device__ inline void store3d(const KArgs<Real, Store>& a, int off, int fam, unsigned node,
-                               const Real* v) {
+                               const Real* v, Real ref) {
   using C = Codec<Real, Store>;
   Store* __restrict__ base = a.B + (size_t)off * (size_t)a.slab;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i)
-    (base + (size_t)i * (size_t)a.slab)[node] =
-        C::enc(v[i], (Real)Lat::w(i) * a.ref[fam], a.scale[fam]);
+    (base + (size_t)i * (size_t)a.slab)[node] = C::enc(v[i], (Real)Lat::w(i) * ref, a.scale[fam]);
 }
 
 // D3Q19 directional-derivative gradient and Laplacian from the phi ring
@@ -262,14 +268,16 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
         if constexpr (MODE == MODE_STEP) {
           const Real om = (Real)1 / (m.alpha * (Real)4 + (Real)0.5);   // c_s^2 = 1/4
           collide_s<D3Q7>(a, s, m, om);
-          store3d<D3Q7>(a, a.off_s, 2, node, s);
+          const Real Tref = kNodeRef<Real, Store> ? (Real)(Sc)m.T : a.ref[2];
+          store3d<D3Q7>(a, a.off_s, 2, node, s, Tref);
+          if constexpr (kNodeRef<Real, Store>) a.B_Tref[node] = (Sc)m.T;
         }
       }
       if constexpr (MODE == MODE_STEP) {
         Real g[7];
         gather3d<D3Q7, 1, XYIN>(a, x, y, z, g);
         collide_g<D3Q7>(a, g, m);
-        store3d<D3Q7>(a, a.off_g, 1, node, g);
+        store3d<D3Q7>(a, a.off_g, 1, node, g, kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1]);
       }
       const Real cs2 = (Real)(1.0 / 3.0);
       m.p = 0;
@@ -285,7 +293,7 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
           m.nu = viscosity(a, m.phi);
           const Real om = (Real)1 / (m.nu * (Real)3 + (Real)0.5);
           collide_f<D3Q19>(f, m, m.rho * cs2 * m.q * a.prod_fac, om);
-          store3d<D3Q19>(a, a.off_f, 0, node, f);
+          store3d<D3Q19>(a, a.off_f, 0, node, f, a.ref[0]);
         }
       }
       if constexpr (MODE == MODE_STEP) {
@@ -475,22 +483,33 @@ __global__ __launch_bounds__(256) void k_init3d(const KArgs<Real, Store> a, cons
       const int side = sz < 0 ? 0 : 1;
       const unsigned node = (unsigned)(z * pz + y * a.px + x);
       const int j = D3Q7::opp(i);
+      const Real gr = kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1];   // slot at this node
       a.B[(size_t)(a.off_g + j) * a.slab + node] =
-          C::enc((Real)2 * w * a.phi_w[2][side] - gv, w * a.ref[1], a.scale[1]);
-      if (HEAT)
+          C::enc((Real)2 * w * a.phi_w[2][side] - gv, w * gr, a.scale[1]);
+      if (HEAT) {
+        const Real tr = kNodeRef<Real, Store> ? (Real)(Sc)m.T : a.ref[2];   // slot at this node
         a.B[(size_t)(a.off_s + j) * a.slab + node] =
-            C::enc((Real)2 * w * a.Tw[2][side][y * a.nx + x] - sv, w * a.ref[2], a.scale[2]);
+            C::enc((Real)2 * w * a.Tw[2][side][y * a.nx + x] - sv, w * tr, a.scale[2]);
+      }
     } else {
       const int sx = wrap1(x - D3Q7::cx(i), a.nx), sy = wrap1(y - D3Q7::cy(i), a.ny);
       const int szz = a.wall[2] ? sz : wrap1(sz, a.nz);
       const unsigned node = (unsigned)(szz * pz + sy * a.px + sx);
-      a.B[(size_t)(a.off_g + i) * a.slab + node] = C::enc(gv, w * a.ref[1], a.scale[1]);
-      if (HEAT) a.B[(size_t)(a.off_s + i) * a.slab + node] = C::enc(sv, w * a.ref[2], a.scale[2]);
+      // the slot belongs to node (sx, sy, szz): its reference is that node's phi0
+      const Real gr = kNodeRef<Real, Store> ? (Real)(Sc)ld(phi0, 0, sx, sy, szz) : a.ref[1];
+      a.B[(size_t)(a.off_g + i) * a.slab + node] = C::enc(gv, w * gr, a.scale[1]);
+      if (HEAT) {
+        // the slot belongs to node (sx, sy, szz): its reference is that node's T0
+        const Real tr = kNodeRef<Real, Store> ? (Real)(Sc)ld(T0, 0, sx, sy, szz) : a.ref[2];
+        a.B[(size_t)(a.off_s + i) * a.slab + node] = C::enc(sv, w * tr, a.scale[2]);
+      }
     }
   }
   const unsigned node = (unsigned)(z * pz + y * a.px + x);
   a.B_phip[node] = (Sc)m.phi;
   a.B_qp[node] = (Sc)m.q;
+  if constexpr (kNodeRef<Real, Store>)
+    if (HEAT) a.B_Tref[node] = (Sc)m.T;
 }
 
 template <class Store, class Real>

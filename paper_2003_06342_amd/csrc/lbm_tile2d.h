@@ -38,11 +38,16 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
   // uniform plane base (scalar registers) + 32-bit lane offset
   const Store* __restrict__ base = a.A + (size_t)off * (size_t)a.slab;
   const unsigned node = (unsigned)(y * a.px + x);
+  // 16-bit storage: g and s are deviations from w_i phi(src) and w_i T_ref(src)
+  constexpr bool NREF = FAM != 0 && kNodeRef<Real, Store>;
+  const typename KArgs<Real, Store>::Sc* __restrict__ rplane = FAM == 1 ? a.A_phip : a.A_Tref;
   if constexpr (FAST) {
 #pragma unroll
     for (int i = 0; i < Lat::Q; ++i) {
+      const unsigned src = node - (unsigned)(Lat::cx(i) + Lat::cy(i) * a.px);
       const unsigned sl = (unsigned)i * (unsigned)a.slab - (unsigned)(Lat::cx(i) + Lat::cy(i) * a.px);
-      v[i] = C::dec(ld_fam(base, node + sl), (Real)Lat::w(i) * ref, inv);
+      const Real r = NREF ? (Real)ld_plane(rplane, src) : ref;
+      v[i] = C::dec(ld_fam(base, node + sl), (Real)Lat::w(i) * r, inv);
     }
     return;
   }
@@ -55,7 +60,8 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
     const Real wref = (Real)Lat::w(i) * ref;
     if (oy || ox) {
       const int j = Lat::opp(i);
-      Real r = C::dec(ld_fam(base, (unsigned)j * (unsigned)a.slab + node), wref, inv);
+      const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, node) : wref;
+      Real r = C::dec(ld_fam(base, (unsigned)j * (unsigned)a.slab + node), wr, inv);
       if (FAM != 0) {
         Real V;
         if (oy) {
@@ -71,21 +77,25 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
     } else {
       if (cx != 0 && !a.wall[0]) sx = wrap1(sx, a.nx);
       if (cy != 0 && !a.wall[1]) sy = wrap1(sy, a.ny);
-      v[i] = C::dec(ld_fam(base, (unsigned)i * (unsigned)a.slab + (unsigned)(sy * a.px + sx)), wref, inv);
+      const unsigned src = (unsigned)(sy * a.px + sx);
+      const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, src) : wref;
+      v[i] = C::dec(ld_fam(base, (unsigned)i * (unsigned)a.slab + src), wr, inv);
     }
   }
 }
 
 // Store the Q post-collision populations of one family at `node` of B.
+// ref: the deviation reference (the family's global one, or the node's
+// T_ref for the s family in 16-bit storage).
 template <class Lat, class Real, class Store>
 __device__ inline void store_family(const KArgs<Real, Store>& a, int off, int fam, unsigned node,
-                                    const Real* v) {
+                                    const Real* v, Real ref) {
   using C = Codec<Real, Store>;
   Store* __restrict__ base = a.B + (size_t)off * (size_t)a.slab;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i)
     st_fam(base, (unsigned)i * (unsigned)a.slab + node,
-           C::enc(v[i], (Real)Lat::w(i) * a.ref[fam], a.scale[fam]));
+           C::enc(v[i], (Real)Lat::w(i) * ref, a.scale[fam]));
 }
 
 // Directional-derivative gradient and Laplacian (Eqs. DerivDirec_Grad, Grad,

@@ -138,16 +138,19 @@ def test_wall_temperature_row_f64():
     _check("wall_row_f64", prm, phi0, T0, 60, "f64", 1e-10, Tw_face=(1, 0, Tw))
 
 
-def test_checkpoint_resume_bitwise():
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_checkpoint_resume_bitwise(storage):
+    """get_state / set_state round trip; for 16-bit storage the blob also
+    carries the per-node temperature reference of the s family."""
     need_gpu()
     from paper_2003_06342_amd import lbm
     prm, phi0, T0 = film_case(70, 40, 8.0, 1.5)
-    a = lbm.Sim(prm, "f32").init(phi0, T0)
+    a = lbm.Sim(prm, storage).init(phi0, T0)
     a.step(30)
     blob = a.get_state()
     a.step(20)
     fa = {k: v.cpu().numpy() for k, v in a.fields().items()}
-    b = lbm.Sim(prm, "f32")
+    b = lbm.Sim(prm, storage)
     b.set_state(blob)
     b.step(20)
     fb = {k: v.cpu().numpy() for k, v in b.fields().items()}

@@ -1,10 +1,12 @@
 """16-bit deviation storage (FP16 / BF16, FP32 arithmetic) against the FP64
-oracle.  Each population is stored as (v - w_i ref) * 2^k with one global
-reference per family, so the storage rounding is about 2^-11 (FP16) or
-2^-8 (BF16) of w_i |T - ref| per population and step.  Measured: FP16 keeps
-phi within 1e-3 relative L2; T is a few 1e-3 (above the 1e-3 target, which
-a global reference cannot reach on the film recipe); BF16 is about 8x
-worse.  Bars below are those measured levels with margin."""
+oracle.  f is stored as (v - w_i ref_f) * 2^k with a global reference; g and
+s as deviations from w_i phi(x) and w_i T(x) of the node x that stored the
+population (per-node references, the lagged phi plane and a T_ref plane).
+
+Measured (relative L2 after 100 steps in 2-D, 40 in 3-D): FP16 phi 7e-6 /
+1.5e-5, T 7e-5 / 7e-5, |u| 5e-4 / 4e-4, p 1.0e-3 / 4e-4 (2-D / 3-D).  The
+per-node references took T from 5e-3 and phi from 5e-4.  BF16 is about 8x
+worse (3 fewer mantissa bits).  The bars are these levels with margin."""
 import numpy as np
 import pytest
 
@@ -41,7 +43,9 @@ def test_deviation_storage(storage, case, steps):
     e16, e32 = compare(g16, ref), compare(g32, ref)
     say(f"[storage16] {case} {storage}: {e16} | f32 {e32}")
     assert all(np.isfinite(v) for v in e16.values())
-    bar_phi, bar_T = (1e-3, 1e-2) if storage == "f16dev" else (1e-2, 1e-1)
-    assert e16["phi"] <= bar_phi and e16["T"] <= bar_T, e16
+    bars = ({"phi": 1e-4, "T": 1e-3, "umag": 2e-3, "p": 3e-3} if storage == "f16dev" else
+            {"phi": 1e-3, "T": 5e-3, "umag": 2e-2, "p": 5e-2})
+    for k, bar in bars.items():
+        assert e16[k] <= bar, (k, e16)
     # the compressed path is never better than FP32 storage
     assert e16["phi"] >= e32["phi"]
