@@ -193,3 +193,28 @@ def test_film_full_size_1024x2048_bench_configuration():
         say(f"[parity] full size {storage}: errors {errs}")
         for k in ("phi", "T", "umag", "p"):
             assert errs[k] <= tol, (storage, k, errs)
+
+
+@pytest.mark.parametrize("nx,ny,bcx,bcy", [(1, 8, "periodic", "periodic"),
+                                           (3, 2, "periodic", "wall"),
+                                           (2, 3, "wall", "periodic"),
+                                           (5, 4, "wall", "periodic")])
+def test_degenerate_tiny_grids_f64(nx, ny, bcx, bcy):
+    """Grids far below one tile: a single periodic column, the smallest
+    walled axes (two nodes, so the 2-node ghost mirrors the far node), and a
+    walled x axis, against the oracle in FP64; and step(0) is a no-op."""
+    need_gpu()
+    prm = I.film2d_params(4, 4)
+    prm["nx"], prm["ny"] = nx, ny
+    prm["bc"] = [bcx, bcy, "periodic"]
+    rng = np.random.default_rng(0)
+    phi0 = 0.5 + 0.3 * rng.standard_normal((1, ny, nx)).clip(-1, 1)
+    T0 = 0.5 + 0.1 * rng.standard_normal((1, ny, nx))
+    say(f"[parity] tiny grid {nx}x{ny} bc=({bcx},{bcy})")
+    g0 = gpu_run(prm, phi0, T0, 0, "f64")
+    assert np.abs(g0["phi"] - phi0).max() < 1e-14
+    ref = oracle_run(prm, phi0, T0, 5)
+    gpu = gpu_run(prm, phi0, T0, 5, "f64")
+    for k in ("phi", "T", "ux", "uy", "p"):
+        err = np.abs(gpu[k] - ref[k]).max()
+        assert err <= 1e-12 * max(1.0, np.abs(ref[k]).max()), (k, err)
