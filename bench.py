@@ -224,6 +224,11 @@ def main():
                                             / HBM_PEAK_GBS, 4))
         for st in ("f64", "f16dev", "bf16dev"):
             record(f"film2d_1024x2048_{st}", prm, fields, st, 27, max(20, args.steps // 4), 5)
+        # the adjoint first: after the 3-D grids (tens of GB) it times slower
+        try:
+            var["adjoint_512x512_f32"] = adjoint_ratio()
+        except Exception as e:  # report, do not hide the headline
+            var["adjoint_512x512_f32"] = {"error": str(e)}
         p3 = I.film3d_params(256)
         f3 = I.film3d_fields(p3, seed=1, h0=32.0, amp=3.0)
         record("film3d_256^3_f32", p3, f3, "f32", 33, 20, 3)
@@ -232,10 +237,7 @@ def main():
         for st in ("f32", "f16dev", "bf16dev"):
             record(f"film3d_512^3_{st}", p5, f5, st, 33, 10, 2)
         del f5
-        try:
-            var["adjoint_512x512_f32"] = adjoint_ratio()
-        except Exception as e:  # report, do not hide the headline
-            var["adjoint_512x512_f32"] = {"error": str(e)}
+        torch.cuda.empty_cache()
         out["variants"] = var
     if args.copy_calib:
         # 512 MiB device copy (16-byte accesses), then a scaled copy of a float
