@@ -172,7 +172,7 @@ def main():
                     help="run one secondary measurement alone (for profiling) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build targets one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU slab decomposition is design-only)", file=sys.stderr)
         sys.exit(2)
     import torch
