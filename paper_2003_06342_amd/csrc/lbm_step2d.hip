@@ -157,13 +157,8 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
   }
 }
 
-// Two 8-wave workgroups per compute unit need at most 128 VGPRs per lane;
-// asking for 4 waves per SIMD keeps the 16-bit storage instantiations there
-// (their codec constants otherwise push them to 3 waves per SIMD, one
-// workgroup per compute unit).  FP64 cannot reach it and stays at 2.
 template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY>
-__global__ __launch_bounds__(Tile2<TY>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_step2d(
-    const KArgs<Real, Store> a) {
+__device__ __forceinline__ void step2d_body(const KArgs<Real, Store>& a) {
   __shared__ Real sphi[Tile2<TY>::R1Y][R1X];
   __shared__ Real sux[Tile2<TY>::R2Y][R2X];
   __shared__ Real suy[Tile2<TY>::R2Y][R2X];
@@ -182,6 +177,21 @@ __global__ __launch_bounds__(Tile2<TY>::NT) __attribute__((amdgpu_waves_per_eu(4
     step_tile2d<Store, Real, NS, HEAT, MODE, true, TY>(a, sphi, sux, suy, x0, y0);
   else
     step_tile2d<Store, Real, NS, HEAT, MODE, false, TY>(a, sphi, sux, suy, x0, y0);
+}
+
+template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY>
+__global__ __launch_bounds__(Tile2<TY>::NT) void k_step2d(const KArgs<Real, Store> a) {
+  step2d_body<Store, Real, NS, HEAT, MODE, TY>(a);
+}
+
+// 16-bit storage: the codec constants and per-node references push the
+// kernel past 128 VGPRs (3 waves per SIMD); asking for 4 keeps it there at
+// the cost of a few SGPR spills (0.200 -> 0.136 ms at 1024 x 2048 before
+// the references were added).
+template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY>
+__global__ __launch_bounds__(Tile2<TY>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_step2d_w4(
+    const KArgs<Real, Store> a) {
+  step2d_body<Store, Real, NS, HEAT, MODE, TY>(a);
 }
 
 // Initialisation: populations = equilibrium - S/2 at the given fields with
@@ -354,15 +364,28 @@ template <class Store, class Real>
 static hipError_t launch_step2d_t(const KArgs<Real, Store>& a, int ns, int heat, int mode,
                                   hipStream_t st) {
   // MODE_MACRO always uses 64-row tiles: its per-block partials are sized by
-  // step2d_blocks
-  const int ty = mode == MODE_STEP ? tile_rows2d(a.nx, a.ny) : 64;
+  // step2d_blocks.  A 4-row tile's g and f are still in L2 when phase 3
+  // pulls them again.  That pays for 16-bit and FP64 storage at every size
+  // and for FP32 on grids of fewer than 512 64-row tiles; FP32 on larger
+  // grids is best at 64 rows.  Measured: 1024 x 2048 FP16 0.101 ms (0.134
+  // with 16 rows), FP64 0.229 (0.253 with 64), FP32 0.127 (0.131 with 4);
+  // 512 x 512 FP32 0.021 ms (0.032 with 16, 0.052 with 64).
+  constexpr bool st16 = sizeof(Store) == 2;
+  constexpr bool small_tiles = st16 || sizeof(Store) == 8;
+  const int ty = mode != MODE_STEP ? 64 : (small_tiles ? 4 : tile_rows2d(a.nx, a.ny));
   const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + ty - 1) / ty);
-#define LBM_L(NSV, HV, MV, TYV)                                                           \
-  hipLaunchKernelGGL((k_step2d<Store, Real, NSV, HV, MV, TYV>), dim3(tiles),              \
-                     dim3(Tile2<TYV>::NT), 0, st, a)
+#define LBM_L(NSV, HV, MV, TYV)                                                                 \
+  do {                                                                                          \
+    if constexpr (st16)                                                                         \
+      hipLaunchKernelGGL((k_step2d_w4<Store, Real, NSV, HV, MV, TYV>), dim3(tiles),            \
+                         dim3(Tile2<TYV>::NT), 0, st, a);                                       \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_step2d<Store, Real, NSV, HV, MV, TYV>), dim3(tiles),               \
+                         dim3(Tile2<TYV>::NT), 0, st, a);                                       \
+  } while (0)
 #define LBM_L2(NSV, HV, MV)            \
   if (ty == 64) LBM_L(NSV, HV, MV, 64); \
-  else LBM_L(NSV, HV, MV, 16)
+  else LBM_L(NSV, HV, MV, 4)
   if (mode == MODE_STEP) {
     if (ns && heat) { LBM_L2(true, true, MODE_STEP); }
     else if (ns) { LBM_L2(true, false, MODE_STEP); }

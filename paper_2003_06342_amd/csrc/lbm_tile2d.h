@@ -8,8 +8,9 @@
 namespace lbm {
 
 // Tiles are 64 columns wide (one wave64 per row) and TY rows high: 64 rows
-// with 512 lanes on large grids, 16 rows with 256 lanes where 64-row tiles
-// would leave compute units idle (fewer than two workgroups per CU).
+// with 512 lanes, or 4 rows with 256 lanes (one row per wave), whose g and f
+// are still in L2 when phase 3 pulls them again (the step launcher chooses;
+// the adjoint's local kernel uses 8 rows).
 constexpr int TX2 = 64, TY2 = 64, NT2 = 512;
 constexpr int R1X = TX2 + 4, R1Y = TY2 + 4;   // phi region (halo 2)
 constexpr int R2X = TX2 + 2, R2Y = TY2 + 2;   // u region (halo 1)
@@ -20,7 +21,7 @@ struct Tile2 {
 };
 inline int tile_rows2d(int nx, int ny) {
   const long long tiles64 = (long long)((nx + TX2 - 1) / TX2) * ((ny + 63) / 64);
-  return tiles64 >= 512 ? 64 : 16;
+  return tiles64 >= 512 ? 64 : 4;
 }
 
 // Pull the Q populations of family FAM (0 f, 1 g, 2 s) arriving at node
