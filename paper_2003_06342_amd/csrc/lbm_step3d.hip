@@ -1,7 +1,8 @@
 // 3-D fused time step for gfx950: D3Q19 for f, D3Q7 for g and s, D3Q19
 // stencils (directional-derivative gradient and Laplacian, Sec. 3.4).
 //
-// 2.5-D blocking: a workgroup (256 lanes) owns a 32 x 16 column of nodes
+// 2.5-D blocking: a workgroup (256 lanes) owns a TX x TY column of nodes (128 x 8
+// for the FP32 step, 32 x 16 otherwise)
 // over a chunk of z planes and marches up z with rolling LDS rings:
 //   phase 1, plane k+2: phi = sum g_bar + q_prev/2 on the tile + 2-halo
 //                       (5-plane ring);
@@ -12,14 +13,26 @@
 // Walls are on z (half-way; bounce-back for f, anti-bounce-back for g, s);
 // x and y are periodic.  A ghost plane beyond a wall is computed at its
 // mirror plane and transformed (2 phi_w - phi, -u).
+#include <type_traits>
+
 #include "lbm_device.h"
 #include "lbm_kernels.h"
 
 namespace lbm {
 
-constexpr int TX3 = 32, TY3 = 16, NT3 = 256, ZC3 = 32;
-constexpr int P1X = TX3 + 4, P1Y = TY3 + 4;   // phi plane region
-constexpr int P2X = TX3 + 2, P2Y = TY3 + 2;   // u plane region
+// Tile shape: TX x TY nodes per plane, marching over ZC planes, 256 lanes.
+template <int TX_, int TY_, int ZC_>
+struct Shape3 {
+  static constexpr int TX = TX_, TY = TY_, ZC = ZC_, NT = 256;
+  static constexpr int P1X = TX + 4, P1Y = TY + 4;   // phi plane region
+  static constexpr int P2X = TX + 2, P2Y = TY + 2;   // u plane region
+};
+// 32 x 16: 16-bit and FP64 storage, and the fields / diagnostics pass.
+// 128 x 8: the FP32 step (256^3 1.46 against 1.77 ms, 512^3 11.0 against
+// 13.3 ms; the wider rows halve the x-halo share of the pulls).  16-bit
+// storage is slower on it (512^3 FP16 14.6 against 12.1 ms).
+using ShapeStd3 = Shape3<32, 16, 32>;
+using ShapeWide3 = Shape3<128, 8, 32>;
 constexpr int NPHI = 5, NU = 3;
 
 __device__ inline int slot5(int p) { return (p + 10) % NPHI; }
@@ -86,8 +99,8 @@ __device__ inline void store3d(const KArgs<Real, Store>& a, int off, int fam, un
 
 // D3Q19 directional-derivative gradient and Laplacian from the phi ring
 // (each direction/opposite pair taken once with weight 2: exact rewrite).
-template <class Real>
-__device__ inline void stencil3d(const Real (*sphi)[P1Y][P1X], int p, int ry, int rx, Real* g,
+template <class S, class Real>
+__device__ inline void stencil3d(const Real (*sphi)[S::P1Y][S::P1X], int p, int ry, int rx, Real* g,
                                  Real& lap) {
   const Real c = sphi[slot5(p)][ry][rx];
   Real gx = 0, gy = 0, gz = 0, l = 0, wsum = 0;
@@ -110,8 +123,9 @@ __device__ inline void stencil3d(const Real (*sphi)[P1Y][P1X], int p, int ry, in
   lap = (l - (Real)2 * wsum * c) * (Real)6;
 }
 
-template <class Real>
-__device__ inline Real divergence3d(const Real (*sphi)[P1Y][P1X], const Real (*su)[3][P2Y][P2X],
+template <class S, class Real>
+__device__ inline Real divergence3d(const Real (*sphi)[S::P1Y][S::P1X],
+                                    const Real (*su)[3][S::P2Y][S::P2X],
                                     int p, int ry, int rx) {
   // ry, rx: u-region coordinates of the node; phi region is offset by 1
   Real d = 0;
@@ -145,9 +159,9 @@ __device__ inline int zplane(int p, int nz, int wall, bool& ghost) {
   return wrapmod(p, nz);
 }
 
-template <class Store, class Real, bool NS, bool HEAT, int MODE, bool XYIN>
-__device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi)[P1Y][P1X],
-                                        Real (*su)[3][P2Y][P2X], int x0, int y0, int z0, int z1) {
+template <class S, class Store, class Real, bool NS, bool HEAT, int MODE, bool XYIN>
+__device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi)[S::P1Y][S::P1X],
+                                        Real (*su)[3][S::P2Y][S::P2X], int x0, int y0, int z0, int z1) {
   using Sc = typename ScalarOf<Store>::T;
   const int tid = threadIdx.x;
   const int pz = a.px * a.ny;
@@ -157,8 +171,8 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
     const int zz = zplane(p, a.nz, a.wall[2], ghost);
     const int s = slot5(p);
     const Real pw = ghost ? a.phi_w[2][p < 0 ? 0 : 1] : (Real)0;
-    for (int k = tid; k < P1X * P1Y; k += NT3) {
-      const int ry = k / P1X, rx = k - ry * P1X;
+    for (int k = tid; k < S::P1X * S::P1Y; k += S::NT) {
+      const int ry = k / S::P1X, rx = k - ry * S::P1X;
       int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
       if (!XYIN) {
         gx = wrapmod(gx, a.nx);
@@ -180,15 +194,15 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
     // a ghost u plane is minus u at the mirror plane, whose phi stencil is in the ring
     const int pm = ghost ? (p < 0 ? -1 - p : 2 * a.nz - 1 - p) : p;
     const int s = slot3(p);
-    for (int k = tid; k < P2X * P2Y; k += NT3) {
-      const int ry = k / P2X, rx = k - ry * P2X;
+    for (int k = tid; k < S::P2X * S::P2Y; k += S::NT) {
+      const int ry = k / S::P2X, rx = k - ry * S::P2X;
       int gx = x0 - 1 + rx, gy = y0 - 1 + ry;
       if (!XYIN) {
         gx = wrapmod(gx, a.nx);
         gy = wrapmod(gy, a.ny);
       }
       Real gphi[3], lphi, rho, mu, F[3];
-      stencil3d<Real>(sphi, pm, ry + 1, rx + 1, gphi, lphi);
+      stencil3d<S, Real>(sphi, pm, ry + 1, rx + 1, gphi, lphi);
       forces(a, sphi[slot5(pm)][ry + 1][rx + 1], gphi, lphi, rho, mu, F);
       Real f[19];
       gather3d<D3Q19, 0, XYIN>(a, gx, gy, zz, f);
@@ -213,14 +227,14 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
   auto phase3 = [&](int k) {
     const int cs = slot5(k);
     (void)cs;
-    for (int t = tid; t < TX3 * TY3; t += NT3) {
-      const int ly = t / TX3, lx = t - ly * TX3;
+    for (int t = tid; t < S::TX * S::TY; t += S::NT) {
+      const int ly = t / S::TX, lx = t - ly * S::TX;
       const int x = x0 + lx, y = y0 + ly, z = k;
       if (x >= a.nx || y >= a.ny) continue;
       const unsigned node = (unsigned)(z * pz + y * a.px + x);
       NodeMacro<Real> m;
       m.phi = sphi[slot5(k)][ly + 2][lx + 2];
-      stencil3d<Real>(sphi, k, ly + 2, lx + 2, m.gphi, m.lphi);
+      stencil3d<S, Real>(sphi, k, ly + 2, lx + 2, m.gphi, m.lphi);
       forces(a, m.phi, m.gphi, m.lphi, m.rho, m.mu, m.F);
       const Real drho = a.rho_g - a.rho_l;
       const Real inrm = rsqrt_t<Real>(m.gphi[0] * m.gphi[0] + m.gphi[1] * m.gphi[1] +
@@ -259,7 +273,7 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
       if constexpr (HEAT) {
         Real s[7];
         gather3d<D3Q7, 2, XYIN>(a, x, y, z, s);
-        if constexpr (NS) m.D = divergence3d<Real>(sphi, su, k, ly + 1, lx + 1);
+        if constexpr (NS) m.D = divergence3d<S, Real>(sphi, su, k, ly + 1, lx + 1);
         Real m0s = 0;
 #pragma unroll
         for (int i = 0; i < 7; ++i) m0s += s[i];
@@ -349,24 +363,24 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
   }
 }
 
-template <class Store, class Real, bool NS, bool HEAT, int MODE>
-__global__ __launch_bounds__(NT3) void k_step3d(const KArgs<Real, Store> a) {
-  __shared__ Real sphi[NPHI][P1Y][P1X];
-  __shared__ Real su[NU][3][P2Y][P2X];
-  const int tx = (a.nx + TX3 - 1) / TX3, ty = (a.ny + TY3 - 1) / TY3;
-  const int zc = (a.nz + ZC3 - 1) / ZC3;
+template <class S, class Store, class Real, bool NS, bool HEAT, int MODE>
+__global__ __launch_bounds__(S::NT) void k_step3d(const KArgs<Real, Store> a) {
+  __shared__ Real sphi[NPHI][S::P1Y][S::P1X];
+  __shared__ Real su[NU][3][S::P2Y][S::P2X];
+  const int tx = (a.nx + S::TX - 1) / S::TX, ty = (a.ny + S::TY - 1) / S::TY;
+  const int zc = (a.nz + S::ZC - 1) / S::ZC;
   const int ntiles = tx * ty * zc;
   int t = blockIdx.x;
   const int full = (ntiles / 8) * 8;
   if (t < full) t = (t % 8) * (full / 8) + t / 8;
   const int ix = t % tx, iy = (t / tx) % ty, iz = t / (tx * ty);
-  const int x0 = ix * TX3, y0 = iy * TY3, z0 = iz * ZC3;
-  const int z1 = min(z0 + ZC3, a.nz);
-  const bool xyin = x0 >= 3 && x0 + TX3 + 3 <= a.nx && y0 >= 3 && y0 + TY3 + 3 <= a.ny;
+  const int x0 = ix * S::TX, y0 = iy * S::TY, z0 = iz * S::ZC;
+  const int z1 = min(z0 + S::ZC, a.nz);
+  const bool xyin = x0 >= 3 && x0 + S::TX + 3 <= a.nx && y0 >= 3 && y0 + S::TY + 3 <= a.ny;
   if (xyin)
-    march3d<Store, Real, NS, HEAT, MODE, true>(a, sphi, su, x0, y0, z0, z1);
+    march3d<S, Store, Real, NS, HEAT, MODE, true>(a, sphi, su, x0, y0, z0, z1);
   else
-    march3d<Store, Real, NS, HEAT, MODE, false>(a, sphi, su, x0, y0, z0, z1);
+    march3d<S, Store, Real, NS, HEAT, MODE, false>(a, sphi, su, x0, y0, z0, z1);
 }
 
 // Initialisation (3-D): equilibrium - S/2 at the initial fields, scattered
@@ -512,12 +526,28 @@ __global__ __launch_bounds__(256) void k_init3d(const KArgs<Real, Store> a, cons
     if (HEAT) a.B_Tref[node] = (Sc)m.T;
 }
 
+template <class S>
+static int blocks3d(int nx, int ny, int nz) {
+  return ((nx + S::TX - 1) / S::TX) * ((ny + S::TY - 1) / S::TY) * ((nz + S::ZC - 1) / S::ZC);
+}
+
 template <class Store, class Real>
 static hipError_t launch_step3d_t(const KArgs<Real, Store>& a, int ns, int heat, int mode,
                                   hipStream_t st) {
-  dim3 grid(step3d_blocks(a.nx, a.ny, a.nz)), block(NT3);
-#define LBM_L(NSV, HV, MV) \
-  hipLaunchKernelGGL((k_step3d<Store, Real, NSV, HV, MV>), grid, block, 0, st, a)
+  // the FP32 step on the wide shape; everything else (and the fields pass,
+  // whose per-block partials are sized by step3d_blocks) on the standard one
+  const bool wide = mode == MODE_STEP && std::is_same<Store, float>::value;
+#define LBM_L(NSV, HV, MV)                                                                     \
+  do {                                                                                         \
+    if (wide)                                                                                  \
+      hipLaunchKernelGGL((k_step3d<ShapeWide3, Store, Real, NSV, HV, MV>),                    \
+                         dim3(blocks3d<ShapeWide3>(a.nx, a.ny, a.nz)), dim3(ShapeWide3::NT), 0, \
+                         st, a);                                                               \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_step3d<ShapeStd3, Store, Real, NSV, HV, MV>),                     \
+                         dim3(blocks3d<ShapeStd3>(a.nx, a.ny, a.nz)), dim3(ShapeStd3::NT), 0,   \
+                         st, a);                                                               \
+  } while (0)
   if (mode == MODE_STEP) {
     if (ns && heat) LBM_L(true, true, MODE_STEP);
     else if (ns) LBM_L(true, false, MODE_STEP);
@@ -549,7 +579,7 @@ static hipError_t launch_init3d_t(const KArgs<Real, Store>& a, int ns, int heat,
 }
 
 int step3d_blocks(int nx, int ny, int nz) {
-  return ((nx + TX3 - 1) / TX3) * ((ny + TY3 - 1) / TY3) * ((nz + ZC3 - 1) / ZC3);
+  return blocks3d<ShapeStd3>(nx, ny, nz);
 }
 
 #define LBM_INST(STORE, REAL)                                                                 \

@@ -84,3 +84,20 @@ def test_drop3d_heat_off_f64():
     r = np.sqrt((x - 15) ** 2 + (y - 13) ** 2 + (z - 14) ** 2)
     phi0 = I.tanh_profile(r - 8.0, p["W"])
     _check("drop3d_f64", p, phi0, None, 30, "f64", 1e-10)
+
+
+def test_film3d_f32_wide_tiles_interior():
+    """The FP32 step's 128 x 8 tiles with interior (seam-free) tiles in x and
+    y and a ragged last tile: 272 x 28 x 20, 30 steps, against the FP32
+    rounding floor of the oracle."""
+    need_gpu()
+    prm, phi0, T0 = film3d_case(272, 28, 20, 6.0, 1.5)
+    n = 30
+    say(f"[parity3d] film3d_f32_wide: steps={n}")
+    floor, ref = fp32_floor(prm, phi0, T0, n)
+    gpu = gpu_run(prm, phi0, T0, n, "f32")
+    errs = compare(gpu, ref)
+    bars = fp32_bars(floor)
+    say(f"[parity3d] film3d_f32_wide: gpu {errs} | floor {floor}")
+    for k in ("phi", "T", "umag", "p"):
+        assert errs[k] <= bars[k], (k, errs, floor)
