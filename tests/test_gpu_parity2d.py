@@ -218,3 +218,15 @@ def test_degenerate_tiny_grids_f64(nx, ny, bcx, bcy):
     for k in ("phi", "T", "ux", "uy", "p"):
         err = np.abs(gpu[k] - ref[k]).max()
         assert err <= 1e-12 * max(1.0, np.abs(ref[k]).max()), (k, err)
+
+
+def test_static_drop_128_500_steps_f64():
+    """The static-drop workload as specified: 128 x 128 periodic, drop radius
+    32, heat off, 500 steps, FP64: parity with the oracle and sum(phi)
+    conserved to rounding on the GPU's FP64 diagnostics."""
+    need_gpu()
+    prm = I.drop_params(128)
+    phi0, _ = I.drop_fields(prm, radius=32.0)
+    errs, gpu, ref = _check("drop128_f64", prm, phi0, None, 500, "f64", 1e-10)
+    m0 = float(phi0.sum())
+    assert abs(gpu["diag"]["mass"] - m0) / m0 < 1e-13

@@ -49,3 +49,25 @@ def test_deviation_storage(storage, case, steps):
         assert e16[k] <= bar, (k, e16)
     # the compressed path is never better than FP32 storage
     assert e16["phi"] >= e32["phi"]
+
+
+def test_compressed_storage_64cubed_instance_of_512cubed_run():
+    """The error instance of the 512^3 compressed-storage workload: a 64^3
+    film (z = 16 + 3 cos cos + noise, seed 6) with the 512^3 run's lattice
+    parameters (its gravity), 300 steps, FP16 / BF16 / FP32 storage against
+    the FP64 oracle.  FP16 stays within 1e-3 on phi, T and |u|."""
+    need_gpu()
+    prm = I.film3d_params(64, wavelength=512.0)
+    phi0, T0 = I.film3d_fields(prm, seed=6, h0=16.0, amp=3.0, wavelength=64.0)
+    steps = 300
+    say(f"[storage16] 64^3 instance: oracle {steps} steps")
+    ref = oracle_run(prm, phi0, T0, steps)
+    errs = {}
+    for st in ("f32", "f16dev", "bf16dev"):
+        errs[st] = compare(gpu_run(prm, phi0, T0, steps, st), ref)
+        say(f"[storage16] 64^3 {st}: {errs[st]}")
+    for k in ("phi", "T", "umag"):
+        assert errs["f16dev"][k] <= 1e-3, ("f16dev", k, errs["f16dev"])
+        assert errs["bf16dev"][k] <= 2e-2, ("bf16dev", k, errs["bf16dev"])
+        assert errs["f32"][k] <= 1e-5, ("f32", k, errs["f32"])
+    assert errs["f16dev"]["p"] <= 3e-3
