@@ -7,8 +7,9 @@ the whole hot path over the grid.  Prints ONE JSON line.
 
   value      MLUPS = nodes * steps / seconds / 1e6 (the paper's metric, Sec. 3.5)
   roofline   HBM-bound: algorithmic bytes per node update (populations read
-             once and written once plus the lagged phi and q) over the kernel
-             time measured with HIP events on the launch stream
+             once and written once plus the lagged phi and q) over the step
+             kernel's average launch duration: HIP events on its launch
+             stream around the timed steps, divided by their number
   cpu_baseline  the FP64 oracle timed on a bounded sample of the same
              workload on this host's cores
 """
@@ -59,23 +60,20 @@ def time_variant(prm, fields, storage, steps, warmup):
     sim.init(*fields)
     sim.step(warmup)
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    # per-launch kernel time with HIP events on the launch stream
-    nev = min(steps, 50)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(nev)]
-    for a, b in evs:
-        a.record(stream)
-        sim.step(1)
-        b.record(stream)
-    torch.cuda.synchronize()
-    kern_ms = sum(a.elapsed_time(b) for a, b in evs) / nev
-    # whole-job timing of exactly `steps` steps
+    stream = sim.stream
+    # whole-job timing of exactly `steps` steps (host clock), and the average
+    # launch duration of the step kernel from HIP events on its launch stream
+    # around the same timed region (each step is one kernel launch)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record(stream)
     sim.step(steps)
+    ev1.record(stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    kern_ms = ev0.elapsed_time(ev1) / steps
     diag = sim.diagnostics(check=False)
     sim.close()
     n = prm["nx"] * prm["ny"] * prm["nz"]

@@ -1,7 +1,7 @@
 // 2-D fused time step (D2Q9 for f, g and s; D2Q9 stencils) for gfx950.
 //
-// One workgroup (512 lanes, 8 wave64) owns a 64 x 64 tile and runs three
-// LDS phases per step:
+// One workgroup owns a tile of 64 columns (one wave64 per row) and runs
+// three LDS phases per step:
 //   1. phi = sum g_bar + q_prev/2 (Eq. Moment_Phi, lagged production) on the
 //      tile plus a 2-node halo, pulled straight from buffer A with the wall
 //      links applied; stored in LDS.  Wall ghosts 2 phi_w - phi_b.
@@ -9,21 +9,29 @@
 //      gradient and Laplacian of phi from LDS (Eqs. Grad, Laplacian),
 //      chemical potential, forces and the first moment of the pulled f.
 //      Stored in LDS.  No-slip ghosts -u_b.
-//   3. every tile node: pull f, g, s, moments (Eqs. Pressure, Moment_Temp),
+//   3. every tile node: pull s, moments (Eqs. Pressure, Moment_Temp),
 //      d_t phi, div(u phi) from LDS, production (Eq. ProductionRate),
 //      equilibria, sources, BGK collision; write to buffer B (pull scheme:
 //      the next step's gather does the streaming).
-// The halo recomputation keeps every step one kernel with no grid-wide
-// synchronisation.  Each population is written once to B.  g and f are
-// pulled twice from A (phases 1-2 and phase 3).  A workgroup's tile is far
-// larger than its share of L2, so the second pull comes from HBM again.
-// The L2-to-memory read requests of one step on the 1024 x 2048 film come
-// to 1.8 times the populations' size.
+// The time step runs one tile node per lane (16 rows on 1024 lanes for FP32,
+// 4 rows on 256 lanes for 16-bit and FP64 storage).  Each lane stages its own
+// node first in phases 1 and 2 and keeps the g and f it pulled there in
+// registers for phase 3, so every population of the tile is read from A
+// once; only the halo nodes are pulled again, by the neighbouring tiles,
+// mostly from L2.  The halo recomputation keeps every step one kernel with
+// no grid-wide synchronisation.  Each population is written once to B.
 #include "lbm_device.h"
 #include "lbm_kernels.h"
 #include "lbm_tile2d.h"
 
 namespace lbm {
+
+// Lanes per workgroup: one tile node per lane for the time step's 4- and
+// 16-row tiles, 512 for the 64-row tiles of the fields pass.
+template <int TY>
+struct StepTile {
+  static constexpr int NT = TY <= 16 ? TX2 * TY : 512;
+};
 
 template <class Store, class Real, bool NS, bool HEAT, int MODE, bool FAST, int TY>
 __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*sphi)[R1X],
@@ -31,12 +39,16 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
   using C = Codec<Real, Store>;
   using Sc = typename ScalarOf<Store>::T;
   const int tid = threadIdx.x;
-  stage2d<Store, Real, NS, HEAT, FAST, TY>(a, sphi, sux, suy, x0, y0);
+  constexpr int NT = StepTile<TY>::NT;
+  // the step keeps the g and f that phases 1-2 pulled for the lane's node
+  constexpr bool CARRY = MODE == MODE_STEP && NT == TX2 * TY;
+  Real gk[9], fk[9];
+  stage2d<Store, Real, NS, HEAT, FAST, TY, NT, CARRY>(a, sphi, sux, suy, x0, y0, gk, fk);
 
   // ---- phase 3: the tile's nodes ------------------------------------------
   double acc_phi = 0, acc_T = 0, acc_phip = 0, acc_umax = 0, acc_bad = 0;
   const int lx = tid % TX2;
-  for (int r = tid / TX2; r < TY; r += Tile2<TY>::NT / TX2) {
+  for (int r = tid / TX2; r < TY; r += NT / TX2) {
     const int x = x0 + lx, y = y0 + r;
     if (x >= a.nx || y >= a.ny) continue;
     const unsigned node = (unsigned)(y * a.px + x);
@@ -100,7 +112,12 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
     }
     if constexpr (MODE == MODE_STEP) {
       Real g[9];
-      gather2d<D2Q9, 1, FAST>(a, x, y, g);
+      if constexpr (CARRY) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = gk[i];
+      } else {
+        gather2d<D2Q9, 1, FAST>(a, x, y, g);
+      }
       collide_g<D2Q9>(a, g, m);
       store_family<D2Q9>(a, a.off_g, 1, node, g,
                          kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1]);
@@ -109,7 +126,12 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
     m.p = 0;
     if constexpr (NS) {
       if constexpr (HEAT) {
-        gather2d<D2Q9, 0, FAST>(a, x, y, f);
+        if constexpr (CARRY) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) f[i] = fk[i];
+        } else {
+          gather2d<D2Q9, 0, FAST>(a, x, y, f);
+        }
 #pragma unroll
         for (int i = 0; i < 9; ++i) m0f += f[i];
       }
@@ -180,7 +202,7 @@ __device__ __forceinline__ void step2d_body(const KArgs<Real, Store>& a) {
 }
 
 template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY>
-__global__ __launch_bounds__(Tile2<TY>::NT) void k_step2d(const KArgs<Real, Store> a) {
+__global__ __launch_bounds__(StepTile<TY>::NT) void k_step2d(const KArgs<Real, Store> a) {
   step2d_body<Store, Real, NS, HEAT, MODE, TY>(a);
 }
 
@@ -189,7 +211,7 @@ __global__ __launch_bounds__(Tile2<TY>::NT) void k_step2d(const KArgs<Real, Stor
 // the cost of a few SGPR spills (0.200 -> 0.136 ms at 1024 x 2048 before
 // the references were added).
 template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY>
-__global__ __launch_bounds__(Tile2<TY>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_step2d_w4(
+__global__ __launch_bounds__(StepTile<TY>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_step2d_w4(
     const KArgs<Real, Store> a) {
   step2d_body<Store, Real, NS, HEAT, MODE, TY>(a);
 }
@@ -364,28 +386,28 @@ template <class Store, class Real>
 static hipError_t launch_step2d_t(const KArgs<Real, Store>& a, int ns, int heat, int mode,
                                   hipStream_t st) {
   // MODE_MACRO always uses 64-row tiles: its per-block partials are sized by
-  // step2d_blocks.  A 4-row tile's g and f are still in L2 when phase 3
-  // pulls them again.  That pays for 16-bit and FP64 storage at every size
-  // and for FP32 on grids of fewer than 512 64-row tiles; FP32 on larger
-  // grids is best at 64 rows.  Measured: 1024 x 2048 FP16 0.101 ms (0.134
-  // with 16 rows), FP64 0.229 (0.253 with 64), FP32 0.127 (0.131 with 4);
-  // 512 x 512 FP32 0.021 ms (0.032 with 16, 0.052 with 64).
+  // step2d_blocks.  The step runs one tile node per lane: 16 rows (1024
+  // lanes) for FP32, 4 rows (256 lanes) for 16-bit and FP64 storage, whose
+  // kernels hold more registers.  Measured at 1024 x 2048: FP32 0.108 ms
+  // (0.120 with 4 rows, 0.110 with 8); FP16 0.092 (0.095 with 8, 0.143 with
+  // 16); FP64 0.204 (0.228 with 8).  At 512 x 512 FP32 0.016 ms (0.018 with
+  // 4 rows).
   constexpr bool st16 = sizeof(Store) == 2;
   constexpr bool small_tiles = st16 || sizeof(Store) == 8;
-  const int ty = mode != MODE_STEP ? 64 : (small_tiles ? 4 : tile_rows2d(a.nx, a.ny));
+  const int ty = mode != MODE_STEP ? 64 : (small_tiles ? 4 : 16);
   const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + ty - 1) / ty);
 #define LBM_L(NSV, HV, MV, TYV)                                                                 \
   do {                                                                                          \
     if constexpr (st16)                                                                         \
       hipLaunchKernelGGL((k_step2d_w4<Store, Real, NSV, HV, MV, TYV>), dim3(tiles),            \
-                         dim3(Tile2<TYV>::NT), 0, st, a);                                       \
+                         dim3(StepTile<TYV>::NT), 0, st, a);                                       \
     else                                                                                        \
       hipLaunchKernelGGL((k_step2d<Store, Real, NSV, HV, MV, TYV>), dim3(tiles),               \
-                         dim3(Tile2<TYV>::NT), 0, st, a);                                       \
+                         dim3(StepTile<TYV>::NT), 0, st, a);                                       \
   } while (0)
-#define LBM_L2(NSV, HV, MV)            \
-  if (ty == 64) LBM_L(NSV, HV, MV, 64); \
-  else LBM_L(NSV, HV, MV, 4)
+#define LBM_L2(NSV, HV, MV)                \
+  if constexpr (small_tiles) LBM_L(NSV, HV, MV, 4); \
+  else LBM_L(NSV, HV, MV, 16)
   if (mode == MODE_STEP) {
     if (ns && heat) { LBM_L2(true, true, MODE_STEP); }
     else if (ns) { LBM_L2(true, false, MODE_STEP); }

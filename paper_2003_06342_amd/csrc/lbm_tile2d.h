@@ -7,10 +7,10 @@
 
 namespace lbm {
 
-// Tiles are 64 columns wide (one wave64 per row) and TY rows high: 64 rows
-// with 512 lanes, or 4 rows with 256 lanes (one row per wave), whose g and f
-// are still in L2 when phase 3 pulls them again (the step launcher chooses;
-// the adjoint's local kernel uses 8 rows).
+// Tiles are 64 columns wide (one wave64 per row) and TY rows high.  Tile2
+// gives the default lane count (512 for 64 rows, else 256); the time step
+// runs one tile node per lane (4 or 16 rows) and the fields pass 64 rows;
+// the adjoint's local kernel uses 8 rows on 256 lanes.
 constexpr int TX2 = 64, TY2 = 64, NT2 = 512;
 constexpr int R1X = TX2 + 4, R1Y = TY2 + 4;   // phi region (halo 2)
 constexpr int R2X = TX2 + 2, R2Y = TY2 + 2;   // u region (halo 1)
@@ -19,10 +19,6 @@ struct Tile2 {
   static constexpr int NT = TY >= 64 ? 512 : 256;
   static constexpr int R1Y = TY + 4, R2Y = TY + 2;
 };
-inline int tile_rows2d(int nx, int ny) {
-  const long long tiles64 = (long long)((nx + TX2 - 1) / TX2) * ((ny + 63) / 64);
-  return tiles64 >= 512 ? 64 : 4;
-}
 
 // Pull the Q populations of family FAM (0 f, 1 g, 2 s) arriving at node
 // (x, y).  A link whose source lies beyond a wall reflects at the node:
@@ -167,19 +163,57 @@ __device__ inline bool to_domain(int& g, int n, int wall) {
 // Mirror of a ghost coordinate across the half-way wall (-1 <-> 0, n <-> n-1).
 __device__ inline int mirror(int g, int n) { return g < 0 ? -1 - g : 2 * n - 1 - g; }
 
+// The halo of a region: halo1_rc enumerates the phi region (tile + 2) minus
+// the tile, halo2_rc the u region (tile + 1) minus the tile: the rows above
+// and below first, then the side columns of the tile rows.
+template <int TY>
+__device__ __forceinline__ void halo1_rc(int h, int& ry, int& rx) {
+  if (h < 2 * R1X) {
+    ry = h / R1X;
+    rx = h - ry * R1X;
+    return;
+  }
+  h -= 2 * R1X;
+  if (h < 2 * R1X) {
+    ry = TY + 2 + h / R1X;
+    rx = h % R1X;
+    return;
+  }
+  h -= 2 * R1X;
+  ry = 2 + (h >> 2);
+  const int c = h & 3;
+  rx = c < 2 ? c : TX2 + c;
+}
+template <int TY>
+__device__ __forceinline__ void halo2_rc(int h, int& ry, int& rx) {
+  if (h < 2 * R2X) {
+    ry = h < R2X ? 0 : TY + 1;
+    rx = h < R2X ? h : h - R2X;
+    return;
+  }
+  h -= 2 * R2X;
+  ry = 1 + (h >> 1);
+  rx = (h & 1) ? R2X - 1 : 0;
+}
+
 // Stage phi on the tile + 2-halo and (NS && HEAT) u on the tile + 1-halo in
 // LDS, with wall ghosts (x ghosts first, then y ghosts, so corners compose).
-template <class Store, class Real, bool NS, bool HEAT, bool FAST, int TY = TY2>
+// NT lanes.  CARRY (NT == TX2 * TY, one tile node per lane): each phase
+// stages the lane's own node first and returns the g it pulled for phi in
+// gk and the f it pulled for u in fk, so the node update does not pull them
+// again; the halo nodes follow.
+template <class Store, class Real, bool NS, bool HEAT, bool FAST, int TY = TY2,
+          int NT = Tile2<TY>::NT, bool CARRY = false>
 __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi)[R1X],
-                                        Real (*sux)[R2X], Real (*suy)[R2X], int x0, int y0) {
+                                        Real (*sux)[R2X], Real (*suy)[R2X], int x0, int y0,
+                                        Real* gk = nullptr, Real* fk = nullptr) {
+  static_assert(!CARRY || NT == TX2 * TY, "CARRY needs one tile node per lane");
   const int tid = threadIdx.x;
   // ---- phase 1: phi on the tile + 2-halo --------------------------------
-  for (int k = tid; k < R1X * Tile2<TY>::R1Y; k += Tile2<TY>::NT) {
-    const int ry = k / R1X, rx = k - ry * R1X;
+  auto phi_node = [&](int ry, int rx, Real* g) {
     int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
     Real v = 0;
     if (FAST || (to_domain(gx, a.nx, a.wall[0]) && to_domain(gy, a.ny, a.wall[1]))) {
-      Real g[9];
       gather2d<D2Q9, 1, FAST>(a, gx, gy, g);
       Real s = 0;
 #pragma unroll
@@ -187,10 +221,25 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
       v = s + (Real)0.5 * (Real)ld_plane(a.A_qp, (unsigned)(gy * a.px + gx));
     }
     sphi[ry][rx] = v;
+  };
+  if constexpr (CARRY) {
+    phi_node(tid / TX2 + 2, tid % TX2 + 2, gk);
+    for (int h = tid; h < R1X * Tile2<TY>::R1Y - TX2 * TY; h += NT) {
+      int ry, rx;
+      halo1_rc<TY>(h, ry, rx);
+      Real g[9];
+      phi_node(ry, rx, g);
+    }
+  } else {
+    for (int k = tid; k < R1X * Tile2<TY>::R1Y; k += NT) {
+      const int ry = k / R1X, rx = k - ry * R1X;
+      Real g[9];
+      phi_node(ry, rx, g);
+    }
   }
   __syncthreads();
   if (!FAST && a.wall[0]) {   // x ghosts first, then y ghosts (corners compose)
-    for (int k = tid; k < R1X * Tile2<TY>::R1Y; k += Tile2<TY>::NT) {
+    for (int k = tid; k < R1X * Tile2<TY>::R1Y; k += NT) {
       const int ry = k / R1X, rx = k - ry * R1X;
       const int gx = x0 - 2 + rx;
       if (gx < 0 || gx >= a.nx) {
@@ -201,7 +250,7 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
     __syncthreads();
   }
   if (!FAST && a.wall[1]) {
-    for (int k = tid; k < R1X * Tile2<TY>::R1Y; k += Tile2<TY>::NT) {
+    for (int k = tid; k < R1X * Tile2<TY>::R1Y; k += NT) {
       const int ry = k / R1X, rx = k - ry * R1X;
       const int gy = y0 - 2 + ry;
       if (gy < 0 || gy >= a.ny) {
@@ -214,15 +263,13 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
 
   // ---- phase 2: u on the tile + 1-halo -----------------------------------
   if constexpr (NS && HEAT) {
-    for (int k = tid; k < R2X * Tile2<TY>::R2Y; k += Tile2<TY>::NT) {
-      const int ry = k / R2X, rx = k - ry * R2X;
+    auto u_node = [&](int ry, int rx, Real* f) {
       int gx = x0 - 1 + rx, gy = y0 - 1 + ry;
       Real ux = 0, uy = 0;
       if (FAST || (to_domain(gx, a.nx, a.wall[0]) && to_domain(gy, a.ny, a.wall[1]))) {
         Real gphi[3], lphi, rho, mu, F[3];
         stencil2d<Real, R1X>(sphi, ry + 1, rx + 1, gphi, lphi);
         forces(a, sphi[ry + 1][rx + 1], gphi, lphi, rho, mu, F);
-        Real f[9];
         gather2d<D2Q9, 0, FAST>(a, gx, gy, f);
         Real mx = 0, my = 0;
 #pragma unroll
@@ -236,10 +283,25 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
       }
       sux[ry][rx] = ux;
       suy[ry][rx] = uy;
+    };
+    if constexpr (CARRY) {
+      u_node(tid / TX2 + 1, tid % TX2 + 1, fk);
+      for (int h = tid; h < R2X * Tile2<TY>::R2Y - TX2 * TY; h += NT) {
+        int ry, rx;
+        halo2_rc<TY>(h, ry, rx);
+        Real f[9];
+        u_node(ry, rx, f);
+      }
+    } else {
+      for (int k = tid; k < R2X * Tile2<TY>::R2Y; k += NT) {
+        const int ry = k / R2X, rx = k - ry * R2X;
+        Real f[9];
+        u_node(ry, rx, f);
+      }
     }
     __syncthreads();
     if (!FAST && a.wall[0]) {
-      for (int k = tid; k < R2X * Tile2<TY>::R2Y; k += Tile2<TY>::NT) {
+      for (int k = tid; k < R2X * Tile2<TY>::R2Y; k += NT) {
         const int ry = k / R2X, rx = k - ry * R2X;
         const int gx = x0 - 1 + rx;
         if (gx < 0 || gx >= a.nx) {
@@ -253,7 +315,7 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
       __syncthreads();
     }
     if (!FAST && a.wall[1]) {
-      for (int k = tid; k < R2X * Tile2<TY>::R2Y; k += Tile2<TY>::NT) {
+      for (int k = tid; k < R2X * Tile2<TY>::R2Y; k += NT) {
         const int ry = k / R2X, rx = k - ry * R2X;
         const int gy = y0 - 1 + ry;
         if (gy < 0 || gy >= a.ny) {
