@@ -352,25 +352,20 @@ __host__ __device__ inline void u_fwd(const NodeConst<Real>& c, const Real* Pf, 
   }
 }
 
-// Adjoint of u_fwd: adds to lPf, and returns adjoints of phi, gphi, lphi.
+// Adjoint of u_fwd at a point whose forward velocity u (u_fwd's output) is
+// known: the populations enter only through m1, so they are not needed.
+// Adds to lPf, and returns adjoints of phi, gphi, lphi.
 template <class Real>
-__host__ __device__ inline void u_adj(const NodeConst<Real>& c, const Real* Pf, Real phi,
-                                      const Real* gphi, Real lphi, const Real* lu, Real* lPf,
-                                      Real& l_phi, Real* l_g, Real& l_lphi) {
+__host__ __device__ inline void u_adj_at(const NodeConst<Real>& c, const Real* u, Real phi,
+                                         const Real* gphi, Real lphi, const Real* lu, Real* lPf,
+                                         Real& l_phi, Real* l_g, Real& l_lphi) {
   const Real rho = phi * c.rho_g + ((Real)1 - phi) * c.rho_l;
   const Real mu = (Real)4 * c.H * phi * (phi - (Real)1) * (phi - (Real)0.5) - c.K * lphi;
-  Real m[2] = {0, 0};
-  for (int i = 0; i < 9; ++i) {
-    m[0] += (Real)W9::cx(i) * Pf[i];
-    m[1] += (Real)W9::cy(i) * Pf[i];
-  }
   Real l_m[2], l_rho = 0, l_mu = 0;
   for (int a = 0; a < 2; ++a) {
-    const Real F = mu * gphi[a] + (rho - c.rho_l) * c.grav[a] + c.body[a];
-    const Real ua = ((Real)3 * m[a] + (Real)0.5 * F) / rho;
     l_m[a] = (Real)3 * lu[a] / rho;
     const Real l_F = (Real)0.5 * lu[a] / rho;
-    l_rho += -lu[a] * ua / rho;
+    l_rho += -lu[a] * u[a] / rho;
     l_mu += l_F * gphi[a];
     l_g[a] = mu * l_F;
     l_rho += l_F * c.grav[a];
@@ -379,6 +374,16 @@ __host__ __device__ inline void u_adj(const NodeConst<Real>& c, const Real* Pf, 
   l_phi = l_mu * (Real)4 * c.H * ((Real)3 * phi * phi - (Real)3 * phi + (Real)0.5) +
           l_rho * (c.rho_g - c.rho_l);
   l_lphi = -c.K * l_mu;
+}
+
+// Adjoint of u_fwd from its inputs.
+template <class Real>
+__host__ __device__ inline void u_adj(const NodeConst<Real>& c, const Real* Pf, Real phi,
+                                      const Real* gphi, Real lphi, const Real* lu, Real* lPf,
+                                      Real& l_phi, Real* l_g, Real& l_lphi) {
+  Real u[2];
+  u_fwd(c, Pf, phi, gphi, lphi, u);
+  u_adj_at(c, u, phi, gphi, lphi, lu, lPf, l_phi, l_g, l_lphi);
 }
 
 // Initial populations (barred equilibria minus half the source at u = 0,

@@ -213,9 +213,8 @@ __global__ __launch_bounds__(256) void k_adj_u2d(const KArgs<Real, Real> a, cons
       }
     }
   }
-  // velocity closure at this node
-  Real Pf[9];
-  gather2d<D2Q9, 0, false>(a, x, y, Pf);
+  // velocity closure at this node (from the forward u: the pulled f enter
+  // it only through their first moment)
   Real P[3][3];
   for (int j = -1; j <= 1; ++j)
     for (int i = -1; i <= 1; ++i) P[j + 1][i + 1] = phi_g(a, b.fphi, x + i, y + j);
@@ -235,17 +234,28 @@ __global__ __launch_bounds__(256) void k_adj_u2d(const KArgs<Real, Real> a, cons
   const Real lap = (l - (Real)2 * ws * phi) * (Real)6;
   Real lPf[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   Real l_phi_u, l_g[2], l_lap;
-  adj::u_adj(b.nc, Pf, phi, g, lap, lu, lPf, l_phi_u, l_g, l_lap);
+  adj::u_adj_at(b.nc, u, phi, g, lap, lu, lPf, l_phi_u, l_g, l_lap);
+  // read-modify-write of distinct slots: all reads first, then all writes,
+  // so that the reads are not serialised behind the writes
+  size_t slot[9];
+  Real old[9], sg[9];
+#pragma unroll
   for (int i = 0; i < 9; ++i) {
-    Real sg;
     int wax, wsd;
-    const size_t slot = pull_slot(a, 0, i, x, y, sg, wax, wsd);
-    b.lP[slot] += sg * lPf[i];
+    slot[i] = pull_slot(a, 0, i, x, y, sg[i], wax, wsd);
+    old[i] = b.lP[slot[i]];
   }
-  b.lloc[(size_t)LL_PHI * a.slab + node] += lphi + l_phi_u;
-  b.lloc[(size_t)LL_GX * a.slab + node] += l_g[0];
-  b.lloc[(size_t)LL_GY * a.slab + node] += l_g[1];
-  b.lloc[(size_t)LL_LAP * a.slab + node] += l_lap;
+  Real* lphi_p = b.lloc + (size_t)LL_PHI * a.slab + node;
+  Real* lgx_p = b.lloc + (size_t)LL_GX * a.slab + node;
+  Real* lgy_p = b.lloc + (size_t)LL_GY * a.slab + node;
+  Real* llap_p = b.lloc + (size_t)LL_LAP * a.slab + node;
+  const Real o_phi = *lphi_p, o_gx = *lgx_p, o_gy = *lgy_p, o_lap = *llap_p;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) b.lP[slot[i]] = old[i] + sg[i] * lPf[i];
+  *lphi_p = o_phi + (lphi + l_phi_u);
+  *lgx_p = o_gx + l_g[0];
+  *lgy_p = o_gy + l_g[1];
+  *llap_p = o_lap + l_lap;
 }
 
 // Transposed stencils for lambda_phi at (x, y) (in-domain or ghost position).
@@ -296,12 +306,17 @@ __global__ __launch_bounds__(256) void k_adj_phi2d(const KArgs<Real, Real> a, co
     lphi_out[(unsigned)(y * a.nx + x)] = lphi;
     return;
   }
+  // read-modify-write of distinct slots: all reads first, then all writes
+  size_t slot[9];
+  Real old[9], sg[9];
+#pragma unroll
   for (int i = 0; i < 9; ++i) {
-    Real sg;
     int wax, wsd;
-    const size_t slot = pull_slot(a, 1, i, x, y, sg, wax, wsd);
-    b.lP[slot] += sg * lphi;
+    slot[i] = pull_slot(a, 1, i, x, y, sg[i], wax, wsd);
+    old[i] = b.lP[slot[i]];
   }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) b.lP[slot[i]] = old[i] + sg[i] * lphi;
   b.lqp[node] = (Real)0.5 * lphi;
 }
 

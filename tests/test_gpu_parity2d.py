@@ -178,10 +178,10 @@ def test_film_f32_1000_steps():
 
 def test_film_full_size_1024x2048_bench_configuration():
     """The benchmark workload itself (1024 x 2048 film, seed 0, h = 64 +
-    4 cos + noise), in the launch configuration bench.py times (64-row
-    tiles, which only grids of at least 512 such tiles use): 4 steps in FP64
-    storage against the oracle within 1e-10, and FP32 storage within 1e-5
-    (four steps are far from the FP32 rounding floor)."""
+    4 cos + noise), in the launch configuration bench.py times (FP32 on
+    64 x 16 tiles of 1024 lanes): 4 steps in FP64 storage against the oracle
+    within 1e-10, and FP32 storage within 1e-5 (four steps are far from the
+    FP32 rounding floor)."""
     need_gpu()
     prm, phi0, T0 = film_case(1024, 2048, 64.0, 4.0)
     nsteps = 4
@@ -218,6 +218,31 @@ def test_degenerate_tiny_grids_f64(nx, ny, bcx, bcy):
     for k in ("phi", "T", "ux", "uy", "p"):
         err = np.abs(gpu[k] - ref[k]).max()
         assert err <= 1e-12 * max(1.0, np.abs(ref[k]).max()), (k, err)
+
+
+@pytest.mark.parametrize("nx,ny,bcx,bcy", [(1, 8, "periodic", "periodic"),
+                                           (3, 2, "periodic", "wall"),
+                                           (2, 3, "wall", "periodic"),
+                                           (5, 4, "wall", "periodic"),
+                                           (70, 19, "periodic", "wall")])
+def test_degenerate_tiny_and_ragged_grids_f32(nx, ny, bcx, bcy):
+    """The FP32 step's 64 x 16 tiles (one node per lane, carried g and f) on
+    grids far below one tile, and on 70 x 19 (a ragged second tile in x and
+    y, with walls): 5 steps against the oracle, max error within 1e-5 of
+    the field scale."""
+    need_gpu()
+    prm = I.film2d_params(4, 4)
+    prm["nx"], prm["ny"] = nx, ny
+    prm["bc"] = [bcx, bcy, "periodic"]
+    rng = np.random.default_rng(1)
+    phi0 = 0.5 + 0.3 * rng.standard_normal((1, ny, nx)).clip(-1, 1)
+    T0 = 0.5 + 0.1 * rng.standard_normal((1, ny, nx))
+    say(f"[parity] tiny grid f32 {nx}x{ny} bc=({bcx},{bcy})")
+    ref = oracle_run(prm, phi0, T0, 5)
+    gpu = gpu_run(prm, phi0, T0, 5, "f32")
+    for k in ("phi", "T", "ux", "uy", "p"):
+        err = np.abs(gpu[k] - ref[k]).max()
+        assert err <= 1e-5 * max(1.0, np.abs(ref[k]).max()), (k, err)
 
 
 def test_static_drop_128_500_steps_f64():
