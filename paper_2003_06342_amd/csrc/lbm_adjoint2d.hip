@@ -7,17 +7,20 @@
 //   K_A  local:   recompute phi, u (LDS, as the forward) and the node inputs,
 //                 apply node_adj: adjoints of the pulled populations P, of
 //                 phi, grad phi, lap phi, u, D at the node; lambda_phi_prev.
-//   K_B  u / D:   transpose of D = div(u phi) (gradient stencil, no-slip and
-//                 Dirichlet ghosts), then the adjoint of the velocity closure.
-//   K_C  phi:     transposed gradient (antisymmetric) and Laplacian
+//   K_BC, in one tiled kernel:
+//     u / D:      transpose of D = div(u phi) (gradient stencil, no-slip and
+//                 Dirichlet ghosts), then the adjoint of the velocity closure
+//                 (on the tile plus a 1-node halo, totals staged in LDS);
+//     phi:        transposed gradient (antisymmetric) and Laplacian
 //                 (symmetric) stencils with Dirichlet ghosts; phi = sum g +
 //                 q_prev/2 distributes lambda_phi to the pulled g and q_prev.
 // The transpose of the pull gather is folded into these kernels: each slot
 // of A is read by exactly one pull, so the adjoint of a pulled population is
-// stored (K_A) or accumulated (K_B for f, K_C for g) straight into the slot
-// it was read from, in a second buffer that becomes lambda_A of the earlier
+// stored (K_A) or accumulated (K_BC, for f and g) straight into the slot it
+// was read from, in a second buffer that becomes lambda_A of the earlier
 // state; anti-bounce-back links of s add 2 w_i lambda to the wall-temperature
-// gradient (K_A).  K_D (push) remains for the seed only.
+// gradient (K_A).  K_C alone (the phi transpose from node fields in memory)
+// serves the initial-condition step; K_D (push) remains for the seed only.
 // Supports at most one walled axis (ghost corners are not differentiated).
 #include "lbm_adjoint.h"
 #include "lbm_adjargs.h"
@@ -180,12 +183,16 @@ __device__ inline void grad_T(const KArgs<Real, Store>& a, const Real* gx, const
 }
 
 // ---------------------------------------------------------------------------
-// K_B: transpose of D = div(u phi) and the velocity-closure adjoint
+// The u transpose at one node: transpose of D = div(u phi) and the
+// velocity-closure adjoint
 // ---------------------------------------------------------------------------
+// At domain node (x, y): lambda of P_a = u_a phi from the transposed gradient
+// of lambda_D (and from the ghost nodes this node mirrors), then the adjoint
+// of the velocity closure.  lPf: the adjoints to add to the node's pulled f;
+// L: the node's lambda of phi, grad phi (x, y) and lap phi after this step.
 template <class Real>
-__global__ __launch_bounds__(256) void k_adj_u2d(const KArgs<Real, Real> a, const AdjArgs<Real> b) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= a.nx || y >= a.ny) return;
+__device__ inline void u_transpose(const KArgs<Real, Real>& a, const AdjArgs<Real>& b, int x, int y,
+                                   Real* lPf, Real* L) {
   const unsigned node = (unsigned)(y * a.px + x);
   const Real* lD = b.lloc + (size_t)LL_D * a.slab;
   const Real phi = b.fphi[node];
@@ -232,30 +239,33 @@ __global__ __launch_bounds__(256) void k_adj_u2d(const KArgs<Real, Real> a, cons
   g[0] *= (Real)3;
   g[1] *= (Real)3;
   const Real lap = (l - (Real)2 * ws * phi) * (Real)6;
-  Real lPf[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) lPf[i] = 0;
   Real l_phi_u, l_g[2], l_lap;
   adj::u_adj_at(b.nc, u, phi, g, lap, lu, lPf, l_phi_u, l_g, l_lap);
-  // read-modify-write of distinct slots: all reads first, then all writes,
-  // so that the reads are not serialised behind the writes
+  L[0] = ldp(b.lloc, a.slab, LL_PHI, node) + lphi + l_phi_u;
+  L[1] = ldp(b.lloc, a.slab, LL_GX, node) + l_g[0];
+  L[2] = ldp(b.lloc, a.slab, LL_GY, node) + l_g[1];
+  L[3] = ldp(b.lloc, a.slab, LL_LAP, node) + l_lap;
+}
+
+// Add v[i] (times the read's sign) to the nine slots that the pull of
+// family fam at (x, y) read; all reads first, then all writes (written as
+// nine separate +=, the reads would wait behind the writes: the compiler
+// cannot prove the slots distinct).
+template <class Real>
+__device__ inline void add_pulled(const KArgs<Real, Real>& a, Real* lP, int fam, int x, int y,
+                                  const Real* v) {
   size_t slot[9];
   Real old[9], sg[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     int wax, wsd;
-    slot[i] = pull_slot(a, 0, i, x, y, sg[i], wax, wsd);
-    old[i] = b.lP[slot[i]];
+    slot[i] = pull_slot(a, fam, i, x, y, sg[i], wax, wsd);
+    old[i] = lP[slot[i]];
   }
-  Real* lphi_p = b.lloc + (size_t)LL_PHI * a.slab + node;
-  Real* lgx_p = b.lloc + (size_t)LL_GX * a.slab + node;
-  Real* lgy_p = b.lloc + (size_t)LL_GY * a.slab + node;
-  Real* llap_p = b.lloc + (size_t)LL_LAP * a.slab + node;
-  const Real o_phi = *lphi_p, o_gx = *lgx_p, o_gy = *lgy_p, o_lap = *llap_p;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) b.lP[slot[i]] = old[i] + sg[i] * lPf[i];
-  *lphi_p = o_phi + (lphi + l_phi_u);
-  *lgx_p = o_gx + l_g[0];
-  *lgy_p = o_gy + l_g[1];
-  *llap_p = o_lap + l_lap;
+  for (int i = 0; i < 9; ++i) lP[slot[i]] = old[i] + sg[i] * v[i];
 }
 
 // Transposed stencils for lambda_phi at (x, y) (in-domain or ghost position).
@@ -279,7 +289,7 @@ __device__ inline Real phi_T(const KArgs<Real, Store>& a, const Real* lg_x, cons
 }
 
 // ---------------------------------------------------------------------------
-// K_C: stencil transposes, phi = sum g + q_prev / 2
+// K_C: stencil transposes, phi = sum g + q_prev / 2 (initial-condition step)
 // ---------------------------------------------------------------------------
 template <class Real>
 __global__ __launch_bounds__(256) void k_adj_phi2d(const KArgs<Real, Real> a, const AdjArgs<Real> b,
@@ -306,18 +316,94 @@ __global__ __launch_bounds__(256) void k_adj_phi2d(const KArgs<Real, Real> a, co
     lphi_out[(unsigned)(y * a.nx + x)] = lphi;
     return;
   }
-  // read-modify-write of distinct slots: all reads first, then all writes
-  size_t slot[9];
-  Real old[9], sg[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    int wax, wsd;
-    slot[i] = pull_slot(a, 1, i, x, y, sg[i], wax, wsd);
-    old[i] = b.lP[slot[i]];
-  }
-#pragma unroll
-  for (int i = 0; i < 9; ++i) b.lP[slot[i]] = old[i] + sg[i] * lphi;
+  const Real v[9] = {lphi, lphi, lphi, lphi, lphi, lphi, lphi, lphi, lphi};
+  add_pulled(a, b.lP, 1, x, y, v);
   b.lqp[node] = (Real)0.5 * lphi;
+}
+
+// ---------------------------------------------------------------------------
+// K_BC: the u transpose and the phi transpose of one step, fused
+// ---------------------------------------------------------------------------
+// A workgroup owns a 64 x TY tile, one node per lane.  Phase U runs the u
+// transpose on the tile plus a 1-node halo (each lane its own node first,
+// then the halo nodes; only a tile node updates its pulled f) and stages the
+// node totals of lambda grad phi and lambda lap phi in LDS, 0 beyond a wall.
+// Phase Phi applies the transposed stencils from LDS (and at the ghost
+// positions a wall-adjacent node mirrors), then phi = sum g + q_prev/2 sends
+// lambda_phi to the nine pulled g and to q_prev.
+template <class Real, int TY>
+__global__ __launch_bounds__(TX2 * TY) void k_adj_uphi2d(const KArgs<Real, Real> a,
+                                                        const AdjArgs<Real> b) {
+  constexpr int NT = TX2 * TY, RX = R2X, RY = TY + 2;
+  __shared__ Real sgx[RY][RX], sgy[RY][RX], slap[RY][RX];
+  const int tiles_x = (a.nx + TX2 - 1) / TX2;
+  const int t = blockIdx.x;
+  const int x0 = (t % tiles_x) * TX2, y0 = (t / tiles_x) * TY;
+  const int tid = threadIdx.x, lx = tid % TX2, r = tid / TX2;
+  const int x = x0 + lx, y = y0 + r;
+  const bool own = x < a.nx && y < a.ny;
+  // ---- phase U ------------------------------------------------------------
+  auto u_at = [&](int ry, int rx, bool mine) -> Real {
+    int gx = x0 - 1 + rx, gy = y0 - 1 + ry;
+    Real L[4] = {0, 0, 0, 0};
+    const bool beyond = (a.wall[0] && (gx < 0 || gx >= a.nx)) || (a.wall[1] && (gy < 0 || gy >= a.ny));
+    if (!beyond) {
+      gx = wrapmod(gx, a.nx);
+      gy = wrapmod(gy, a.ny);
+      Real lPf[9];
+      u_transpose(a, b, gx, gy, lPf, L);
+      if (mine) add_pulled(a, b.lP, 0, gx, gy, lPf);
+    }
+    sgx[ry][rx] = L[1];
+    sgy[ry][rx] = L[2];
+    slap[ry][rx] = L[3];
+    return L[0];
+  };
+  const Real lphi_u = u_at(r + 1, lx + 1, own);
+  for (int h = tid; h < RX * RY - NT; h += NT) {
+    int ry, rx;
+    halo2_rc<TY>(h, ry, rx);
+    u_at(ry, rx, false);
+  }
+  __syncthreads();
+  if (!own) return;
+  // ---- phase Phi ----------------------------------------------------------
+  // transposed gradient and Laplacian at region position (ry, rx); points
+  // outside the region lie beyond a wall (ghost evaluations only) and are 0
+  auto phiT = [&](int ry, int rx, bool self) -> Real {
+    auto F = [&](const Real (*s)[RX], int yy, int xx) -> Real {
+      return (yy < 0 || yy >= RY || xx < 0 || xx >= RX) ? (Real)0 : s[yy][xx];
+    };
+    Real ox = 0, oy = 0, l = 0, ws = 0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      if (i > D2Q9::opp(i)) continue;
+      const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+      const Real w = (Real)D2Q9::w(i);
+      if (cx) ox += w * (Real)cx * (F(sgx, ry - cy, rx - cx) - F(sgx, ry + cy, rx + cx));
+      if (cy) oy += w * (Real)cy * (F(sgy, ry - cy, rx - cx) - F(sgy, ry + cy, rx + cx));
+      l += w * (F(slap, ry - cy, rx - cx) + F(slap, ry + cy, rx + cx));
+      ws += w;
+    }
+    Real out = (Real)3 * ox + (Real)3 * oy + (Real)6 * l;
+    if (self) out -= (Real)12 * ws * slap[ry][rx];
+    return out;
+  };
+  Real lphi = lphi_u + phiT(r + 1, lx + 1, true);
+  // ghosts 2 phi_w - phi(mirror): their transposed value flows back with -1
+  for (int ax = 0; ax < 2; ++ax) {
+    if (!a.wall[ax]) continue;
+    const int n = ax == 0 ? a.nx : a.ny, c = ax == 0 ? x : y;
+    for (int side = 0; side < 2; ++side) {
+      if ((side == 0 && c != 0) || (side == 1 && c != n - 1)) continue;
+      const int gx = ax == 0 ? (side == 0 ? -1 : a.nx) : x;
+      const int gy = ax == 1 ? (side == 0 ? -1 : a.ny) : y;
+      lphi -= phiT(gy - (y0 - 1), gx - (x0 - 1), false);
+    }
+  }
+  const Real v[9] = {lphi, lphi, lphi, lphi, lphi, lphi, lphi, lphi, lphi};
+  add_pulled(a, b.lP, 1, x, y, v);
+  b.lqp[(unsigned)(y * a.px + x)] = (Real)0.5 * lphi;
 }
 
 // ---------------------------------------------------------------------------
@@ -458,8 +544,9 @@ hipError_t launch_adj_step2d_t(const KArgs<Real, Real>& a, const AdjArgs<Real>& 
   constexpr int ty = 8;
   const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + ty - 1) / ty);
   hipLaunchKernelGGL((k_adj_local2d<Real, ty>), dim3(tiles), dim3(Tile2<ty>::NT), 0, st, a, b);
-  hipLaunchKernelGGL(k_adj_u2d<Real>, node_grid(a), dim3(256), 0, st, a, b);
-  hipLaunchKernelGGL(k_adj_phi2d<Real>, node_grid(a), dim3(256), 0, st, a, b, (Real*)nullptr);
+  constexpr int tyb = 8;
+  const int tiles_b = ((a.nx + TX2 - 1) / TX2) * ((a.ny + tyb - 1) / tyb);
+  hipLaunchKernelGGL((k_adj_uphi2d<Real, tyb>), dim3(tiles_b), dim3(TX2 * tyb), 0, st, a, b);
   return hipGetLastError();
 }
 

@@ -71,6 +71,50 @@ def test_adjoint_matches_oracle_autograd_f64():
     assert e_phi < 1e-9 and e_T0 < 1e-9 and e_tw < 1e-9
 
 
+def test_adjoint_x_walls_matches_oracle_autograd_f64():
+    """The film turned on its side: walls on x (heated face x = 0), periodic
+    y, gravity along -x; 20 x 70 nodes (one ragged tile in x, a ragged last
+    tile row in y), 12 steps,
+    gradients against the oracle's reverse pass (exercises the x ghosts of
+    the transposed stencils)."""
+    need_gpu()
+    prm0, phi0t, T0t_, Twt = film(70, 20, 6.0, 1.5, g=2e-4)
+    prm = dict(prm0)
+    prm["nx"], prm["ny"] = prm0["ny"], prm0["nx"]
+    prm["bc"] = ["wall", "periodic", "periodic"]
+    prm["phi_wall"] = [prm0["phi_wall"][1], [0.0, 0.0], [0.0, 0.0]]
+    prm["T_wall"] = [prm0["T_wall"][1], [0.0, 0.0], [0.0, 0.0]]
+    prm["gravity"] = [prm0["gravity"][1], 0.0, 0.0]
+    phi0 = np.ascontiguousarray(phi0t.transpose(0, 2, 1))
+    T0 = np.ascontiguousarray(T0t_.transpose(0, 2, 1))
+    Tw = Twt
+    n = 12
+    say(f"[adjoint] x walls {prm['nx']}x{prm['ny']}, {n} steps")
+    phi = torch.tensor(phi0, dtype=F64, requires_grad=True)
+    T0v = torch.tensor(T0, dtype=F64, requires_grad=True)
+    tw = torch.tensor(Tw, dtype=F64, requires_grad=True)
+    M = Model(prm, T_wall_faces={(0, 0): tw.reshape(1, -1, 1)})
+    V = M.fields(M.run(M.init(phi, T0v), n))["phi"].mean()
+    V.backward()
+    from paper_2003_06342_amd import lbm
+    sim = lbm.Sim(prm, "f64")
+    sim.set_wall_T(0, 0, Tw)
+    sim.init(phi0, T0)
+    sim.forward_taped(n)
+    Vg = float(sim.fields(("phi",))["phi"].double().mean())
+    N = prm["nx"] * prm["ny"]
+    g = sim.backward(np.full((prm["ny"], prm["nx"]), 1.0 / N), tw_face=(0, 0))
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    sim.sync()
+    sim.close()
+    assert Vg == pytest.approx(float(V), rel=1e-12)
+    e_phi = rel_l2(g["phi0"], phi.grad.numpy()[0])
+    e_T0 = rel_l2(g["T0"], T0v.grad.numpy()[0])
+    e_tw = rel_l2(g["Tw"], tw.grad.numpy())
+    say(f"[adjoint] x walls rel L2 vs oracle: dphi0 {e_phi:.2e} dT0 {e_T0:.2e} dTw {e_tw:.2e}")
+    assert e_phi < 1e-9 and e_T0 < 1e-9 and e_tw < 1e-9
+
+
 def test_adjoint_sqrtT_segments_match_oracle():
     """31 steps: several tape segments of ceil(sqrt(31)) = 6 steps."""
     need_gpu()
