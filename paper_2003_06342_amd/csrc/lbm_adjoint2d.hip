@@ -538,13 +538,14 @@ static dim3 node_grid(const KArgs<Real, Real>& a) {
 
 template <class Real>
 hipError_t launch_adj_step2d_t(const KArgs<Real, Real>& a, const AdjArgs<Real>& b, hipStream_t st) {
-  // 8-row tiles: the re-gathered populations of a tile are still in L2
-  // (measured at 512 x 512 FP32: 97 us per reverse step against 111 with 16
-  // rows and 101 with 4)
+  // Local kernel on 8-row tiles: the re-gathered populations of a tile are
+  // still in L2 (512 x 512 FP32, whole reverse step: 71 us against 75 with
+  // 4 rows and 86 with 16).  u/phi transposes on 64 x 16 tiles of 1024
+  // lanes (70.5 us against 71.2 with 8 rows and 72.7 with 4).
   constexpr int ty = 8;
   const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + ty - 1) / ty);
   hipLaunchKernelGGL((k_adj_local2d<Real, ty>), dim3(tiles), dim3(Tile2<ty>::NT), 0, st, a, b);
-  constexpr int tyb = 8;
+  constexpr int tyb = 16;
   const int tiles_b = ((a.nx + TX2 - 1) / TX2) * ((a.ny + tyb - 1) / tyb);
   hipLaunchKernelGGL((k_adj_uphi2d<Real, tyb>), dim3(tiles_b), dim3(TX2 * tyb), 0, st, a, b);
   return hipGetLastError();
