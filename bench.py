@@ -12,6 +12,9 @@ the whole hot path over the grid.  Prints ONE JSON line.
              stream around the timed steps, divided by their number
   cpu_baseline  the FP64 oracle timed on a bounded sample of the same
              workload on this host's cores
+  context.pattern_probe  a compute-free kernel with the step's exact HBM
+             access pattern, and a plain copy of the same bytes: the
+             bandwidth the device gives this pattern
 """
 from __future__ import annotations
 
@@ -157,6 +160,54 @@ def traffic_entry(name: str, nodes: int):
     return d.get("bytes_per_launch")
 
 
+def pattern_probe(nx=1024, ny=2048, reps=50):
+    """Bandwidth of the step's HBM access pattern with no arithmetic: the
+    probe kernel copies the 29 planes of the FP32 2-D step (27 populations
+    read at the pull offsets, phi_prev and q_prev) over the interior nodes
+    of the headline grid; beside it, a plain device copy of the same byte
+    count.  Both timed with HIP events on the current stream."""
+    import ctypes
+    import torch
+    path = os.path.join(ROOT, "paper_2003_06342_amd", "libstream_probe.so")
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    lib.stream_probe_pull_pattern.restype = ctypes.c_int
+    lib.stream_probe_pull_pattern.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_void_p]
+    n = 29 * nx * ny
+    a = torch.rand(n, device="cuda")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+
+    def probe():
+        rc = lib.stream_probe_pull_pattern(a.data_ptr(), b.data_ptr(), nx, ny, st.cuda_stream)
+        if rc != 0:
+            raise RuntimeError(f"probe launch failed ({rc})")
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_p = timed(probe)
+    ms_c = timed(lambda: b.copy_(a))
+    bytes_p = 2 * 29 * 4 * (nx - 2) * (ny - 2)
+    bytes_c = 2 * 4 * n
+    del a, b
+    torch.cuda.empty_cache()
+    return {"pull_pattern_ms": round(ms_p, 5), "pull_pattern_GBs": round(bytes_p / ms_p / 1e6, 1),
+            "copy_same_bytes_ms": round(ms_c, 5),
+            "copy_same_bytes_GBs": round(bytes_c / ms_c / 1e6, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +261,8 @@ def main():
     }
     if not head["finite"]:
         out["warning"] = "non-finite values after the timed run"
+    # the device's bandwidth on this kernel's access pattern without compute
+    out["context"]["pattern_probe"] = pattern_probe(nx, ny)
     if not args.no_variants:
         var = {}
 

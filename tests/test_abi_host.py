@@ -99,3 +99,18 @@ def test_walled_axis_needs_two_nodes(lib):
     assert _status(I.film2d_params(16, 2))[0] == lbm.LBM_OK
     prm = I.film2d_params(1, 8)   # x periodic: one column is allowed
     assert _status(prm)[0] == lbm.LBM_OK
+
+
+def test_stream_probe_library_loads_and_checks_arguments():
+    """The measurement probe bench.py times beside the step (its own
+    library, outside the C ABI) is built, exports its launcher, and rejects
+    null buffers and grids below 3 x 3 before any device call."""
+    path = os.path.join(os.path.dirname(lbm.LIB_PATH), "libstream_probe.so")
+    if not os.path.exists(path):
+        pytest.fail("libstream_probe.so is not built (run __graft_entry__.build())")
+    p = C.CDLL(path)
+    f = p.stream_probe_pull_pattern
+    f.restype = C.c_int
+    f.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+    assert f(None, None, 64, 64, None) != 0
+    assert f(C.c_void_p(16), C.c_void_p(32), 2, 64, None) != 0
