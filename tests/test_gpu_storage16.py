@@ -75,3 +75,23 @@ def test_compressed_storage_64cubed_instance_of_512cubed_run():
         assert errs["bf16dev"][k] <= 2e-2, ("bf16dev", k, errs["bf16dev"])
     assert errs["f16dev"]["p"] <= 3e-3
     assert errs["f32"]["phi"] <= 1e-5 and errs["f32"]["T"] <= 1e-5, errs["f32"]
+
+
+def test_deviation_storage_full_size_bench_grid():
+    """FP16 and BF16 storage on the benchmark grid itself (1024 x 2048 film,
+    seed 0), in the launch configuration bench.py times (64 x 4 tiles, one
+    node per lane): 20 steps against the FP64 oracle, with the 2-D bars
+    above."""
+    need_gpu()
+    prm = I.film2d_params(1024, 2048)
+    phi0, T0, _ = I.film2d_fields(prm, seed=0, h0=64.0, amp=4.0)
+    n = 20
+    say(f"[storage16] full size 1024x2048: oracle {n} steps")
+    ref = oracle_run(prm, phi0, T0, n)
+    for storage, bars in (("f16dev", {"phi": 1e-4, "T": 1e-3, "umag": 2e-3, "p": 3e-3}),
+                          ("bf16dev", {"phi": 1e-3, "T": 5e-3, "umag": 2e-2, "p": 5e-2})):
+        e = compare(gpu_run(prm, phi0, T0, n, storage), ref)
+        say(f"[storage16] full size {storage}: {e}")
+        for k, bar in bars.items():
+            assert e[k] <= bar, (storage, k, e)
+
