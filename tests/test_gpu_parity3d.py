@@ -101,3 +101,22 @@ def test_film3d_f32_wide_tiles_interior():
     say(f"[parity3d] film3d_f32_wide: gpu {errs} | floor {floor}")
     for k in ("phi", "T", "umag", "p"):
         assert errs[k] <= bars[k], (k, errs, floor)
+
+
+def test_film3d_full_size_256_bench_configuration():
+    """The 3-D benchmark workload itself (256^3 film, seed 1, z = 32 +
+    3 cos cos + noise) in the launch configuration bench.py times (FP32 on
+    128 x 8 tiles, FP64 on 32 x 16): 2 steps against the oracle, FP64 within
+    1e-10 and FP32 within 1e-5 (two steps are far from the FP32 rounding
+    floor)."""
+    need_gpu()
+    prm = I.film3d_params(256)
+    phi0, T0 = I.film3d_fields(prm, seed=1, h0=32.0, amp=3.0)
+    n = 2
+    say(f"[parity3d] full size 256^3: oracle {n} steps")
+    ref = oracle_run(prm, phi0, T0, n)
+    for storage, tol in (("f64", 1e-10), ("f32", 1e-5)):
+        errs = compare(gpu_run(prm, phi0, T0, n, storage), ref)
+        say(f"[parity3d] full size {storage}: {errs}")
+        for k in ("phi", "T", "umag", "p"):
+            assert errs[k] <= tol, (storage, k, errs)
