@@ -217,7 +217,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (HBM counter calibration)")
-    ap.add_argument("--only", choices=["film3d256", "adjoint"],
+    ap.add_argument("--only", choices=["film3d256", "adjoint", "film2d_f16dev"],
                     help="run one secondary measurement alone (for profiling) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -235,6 +235,12 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps({"adjoint_512x512_f32": adjoint_ratio()}), flush=True)
+        return
+    if args.only == "film2d_f16dev":
+        p2 = I.film2d_params(1024, 2048)
+        f2 = I.film2d_fields(p2, seed=0, h0=64.0, amp=4.0)[:2]
+        r = time_variant(p2, f2, "f16dev", args.steps, args.warmup)
+        print(json.dumps({"film2d_1024x2048_f16dev": r}), flush=True)
         return
 
     nx, ny = 1024, 2048
