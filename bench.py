@@ -217,7 +217,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (HBM counter calibration)")
-    ap.add_argument("--only", choices=["film3d256", "adjoint", "film2d_f16dev"],
+    ap.add_argument("--only", choices=["film3d256", "adjoint", "film2d_f16dev", "film3d512_f32",
+                                       "film3d512_f16dev"],
                     help="run one secondary measurement alone (for profiling) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -235,6 +236,13 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps({"adjoint_512x512_f32": adjoint_ratio()}), flush=True)
+        return
+    if args.only in ("film3d512_f32", "film3d512_f16dev"):
+        st = args.only.split("_")[1]
+        p5 = I.film3d_params(512)
+        f5 = I.film3d_fields(p5, seed=5, h0=64.0, amp=6.0)
+        r = time_variant(p5, f5, st, args.steps, args.warmup)
+        print(json.dumps({f"film3d_512^3_{st}": r}), flush=True)
         return
     if args.only == "film2d_f16dev":
         p2 = I.film2d_params(1024, 2048)
