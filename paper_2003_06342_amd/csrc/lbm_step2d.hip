@@ -206,10 +206,9 @@ __global__ __launch_bounds__(StepTile<TY>::NT) void k_step2d(const KArgs<Real, S
   step2d_body<Store, Real, NS, HEAT, MODE, TY>(a);
 }
 
-// 16-bit storage: the codec constants and per-node references push the
-// kernel past 128 VGPRs (3 waves per SIMD); asking for 4 keeps it there at
-// the cost of a few SGPR spills (0.200 -> 0.136 ms at 1024 x 2048 before
-// the references were added).
+// 16-bit storage: at most 128 VGPRs (4 waves per SIMD).  The codec constants
+// and per-node references pushed the 64-row tile kernel past that (0.200 ->
+// 0.136 ms at 1024 x 2048 with the cap); the 4-row carry kernel needs 72.
 template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY>
 __global__ __launch_bounds__(StepTile<TY>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_step2d_w4(
     const KArgs<Real, Store> a) {
