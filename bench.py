@@ -35,12 +35,19 @@ METRIC = "MLUPS + % HBM roofline, FP32 & FP16-store vs FP64 oracle error; adjoin
 
 def bytes_per_node(dim: int, q_total: int, storage: str) -> int:
     """Algorithmic bytes per node update: every population read once and
-    written once, plus phi_prev and q_prev (and, for 16-bit storage, the
-    per-node temperature reference of the s family) read and written."""
+    written once, plus phi_prev and q_prev read and written (FP32, FP64 for
+    FP64 storage)."""
     pe = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}[storage]
     se = 8 if storage == "f64" else 4
-    nsc = 3 if pe == 2 else 2
-    return q_total * pe * 2 + nsc * se * 2
+    return q_total * pe * 2 + 2 * se * 2
+
+
+def impl_bytes_per_node(dim: int, q_total: int, storage: str) -> int:
+    """Bytes per node update this implementation moves at best: the
+    algorithmic bytes plus, for 16-bit storage, the per-node temperature
+    reference plane of the s family (FP32, read and written)."""
+    extra = 2 * 4 if storage in ("f16dev", "bf16dev") else 0
+    return bytes_per_node(dim, q_total, storage) + extra
 
 
 # sources of the dominant kernel (k_step2d); HBM counters recorded under
@@ -130,24 +137,48 @@ def adjoint_ratio(nx=512, ny=512, nsteps=200):
                 ratio_adjoint_kernels=round(t_adj / t_fwd, 3))
 
 
-def cpu_baseline(prm, fields, budget_s=20.0):
-    """FP64 oracle on the same grid for as many whole steps as fit ~budget_s."""
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prm, fields, budget_s=12.0):
+    """FP64 oracle on the same grid, timed on this host's cores: as many
+    whole steps as fit about budget_s with all threads torch uses, then
+    with one thread (at most a few steps)."""
     import torch
     from oracle.lbm_oracle import Model
     M = Model(prm)
-    st = M.init(*fields)
-    t0 = time.perf_counter()
-    st = M.step(st)
-    one = time.perf_counter() - t0
-    k = max(1, min(20, int(budget_s / max(one, 1e-3)) - 1))
-    t0 = time.perf_counter()
-    for _ in range(k):
-        st = M.step(st)
-    dt = time.perf_counter() - t0
     n = prm["nx"] * prm["ny"] * prm["nz"]
-    return dict(value=n * k / dt / 1e6, unit="MLUPS", cores=torch.get_num_threads(), kind="oracle",
-                sample=f"{k} FP64 oracle steps of the full {prm['nx']}x{prm['ny']} film grid "
-                       f"after 1 untimed step ({dt:.1f} s)")
+
+    def timed(budget, kmax):
+        st = M.init(*fields)
+        t0 = time.perf_counter()
+        st = M.step(st)
+        one = time.perf_counter() - t0
+        k = max(1, min(kmax, int(budget / max(one, 1e-3)) - 1))
+        t0 = time.perf_counter()
+        for _ in range(k):
+            st = M.step(st)
+        return k, time.perf_counter() - t0
+
+    nthreads = torch.get_num_threads()
+    k, dt = timed(budget_s, 20)
+    torch.set_num_threads(1)
+    try:
+        k1, dt1 = timed(budget_s, 4)
+    finally:
+        torch.set_num_threads(nthreads)
+    return dict(value=n * k / dt / 1e6, unit="MLUPS", cores=nthreads, kind="oracle",
+                value_1thread=n * k1 / dt1 / 1e6, cpu_model=cpu_model(), nproc=os.cpu_count(),
+                sample=f"{k} FP64 oracle steps of the full {prm['nx']}x{prm['ny']} film grid on "
+                       f"{nthreads} threads ({dt:.1f} s), and {k1} on 1 thread ({dt1:.1f} s), each "
+                       f"after 1 untimed step")
 
 
 def traffic_entry(name: str, nodes: int):
@@ -164,17 +195,21 @@ def pattern_probe(nx=1024, ny=2048, reps=50):
     """Bandwidth of the step's HBM access pattern with no arithmetic: the
     probe kernel copies the 29 planes of the FP32 2-D step (27 populations
     read at the pull offsets, phi_prev and q_prev) over the interior nodes
-    of the headline grid; beside it, a plain device copy of the same byte
-    count.  Both timed with HIP events on the current stream."""
+    of the headline grid.  Beside it, copies of the same byte count: a
+    hand-written 16-byte streaming copy (plain and non-temporal) and torch's
+    copy_.  All timed with HIP events on the launch stream."""
     import ctypes
     import torch
-    path = os.path.join(ROOT, "paper_2003_06342_amd", "libstream_probe.so")
+    path = os.path.join(ROOT, "benchprobe", "libstream_probe.so")
     if not os.path.exists(path):
         raise ImportError(f"{path} not built; run __graft_entry__.build() first")
     lib = ctypes.CDLL(path)
     lib.stream_probe_pull_pattern.restype = ctypes.c_int
     lib.stream_probe_pull_pattern.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
-                                           ctypes.c_int, ctypes.c_void_p]
+                                              ctypes.c_int, ctypes.c_void_p]
+    lib.stream_probe_copy16.restype = ctypes.c_int
+    lib.stream_probe_copy16.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong,
+                                        ctypes.c_int, ctypes.c_void_p]
     n = 29 * nx * ny
     a = torch.rand(n, device="cuda")
     b = torch.empty_like(a)
@@ -184,6 +219,13 @@ def pattern_probe(nx=1024, ny=2048, reps=50):
         rc = lib.stream_probe_pull_pattern(a.data_ptr(), b.data_ptr(), nx, ny, st.cuda_stream)
         if rc != 0:
             raise RuntimeError(f"probe launch failed ({rc})")
+
+    def copy16(nt):
+        def run():
+            rc = lib.stream_probe_copy16(a.data_ptr(), b.data_ptr(), 4 * n, nt, st.cuda_stream)
+            if rc != 0:
+                raise RuntimeError(f"copy16 launch failed ({rc})")
+        return run
 
     def timed(fn):
         for _ in range(5):
@@ -198,14 +240,20 @@ def pattern_probe(nx=1024, ny=2048, reps=50):
         return e0.elapsed_time(e1) / reps
 
     ms_p = timed(probe)
+    ms_16 = timed(copy16(0))
+    ms_16nt = timed(copy16(1))
     ms_c = timed(lambda: b.copy_(a))
     bytes_p = 2 * 29 * 4 * (nx - 2) * (ny - 2)
     bytes_c = 2 * 4 * n
     del a, b
     torch.cuda.empty_cache()
-    return {"pull_pattern_ms": round(ms_p, 5), "pull_pattern_GBs": round(bytes_p / ms_p / 1e6, 1),
-            "copy_same_bytes_ms": round(ms_c, 5),
-            "copy_same_bytes_GBs": round(bytes_c / ms_c / 1e6, 1)}
+    gbs = lambda by, ms: round(by / ms / 1e6, 1)
+    return {"pull_pattern_ms": round(ms_p, 5), "pull_pattern_GBs": gbs(bytes_p, ms_p),
+            "copy16_same_bytes_ms": round(ms_16, 5), "copy16_same_bytes_GBs": gbs(bytes_c, ms_16),
+            "copy16_nt_same_bytes_ms": round(ms_16nt, 5),
+            "copy16_nt_same_bytes_GBs": gbs(bytes_c, ms_16nt),
+            "torch_copy_same_bytes_ms": round(ms_c, 5),
+            "torch_copy_same_bytes_GBs": gbs(bytes_c, ms_c)}
 
 
 def main():
@@ -283,10 +331,13 @@ def main():
         def record(name, prm_v, fields_v, st, q, steps, warm):
             r = time_variant(prm_v, fields_v, st, steps, warm)
             b = bytes_per_node(prm_v["dim"], q, st)
+            bi = impl_bytes_per_node(prm_v["dim"], q, st)
+            rate = r["nodes"] / (r["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
             var[name] = dict(mlups=round(r["mlups"], 1), kernel_ms=round(r["kernel_ms"], 5),
-                             bytes_per_node=b,
-                             hbm_frac=round(b * r["nodes"] / (r["kernel_ms"] * 1e-3) / 1e9
-                                            / HBM_PEAK_GBS, 4))
+                             bytes_per_node=b, hbm_frac=round(b * rate, 4))
+            if bi != b:   # 16-bit storage: the per-node T_ref plane, reported apart
+                var[name]["impl_bytes_per_node"] = bi
+                var[name]["impl_hbm_frac"] = round(bi * rate, 4)
         for st in ("f64", "f16dev", "bf16dev"):
             record(f"film2d_1024x2048_{st}", prm, fields, st, 27, max(20, args.steps // 4), 5)
         # the adjoint first: after the 3-D grids (tens of GB) it times slower

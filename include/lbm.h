@@ -75,8 +75,38 @@ enum {
   LBM_HEAT = 2,          /* evolve s (else T = 0 and no phase change)       */
   LBM_PHASE_CHANGE = 4,  /* production q = m'''/rho_g of Eq. ProductionRate */
   LBM_VISC_LINEAR = 8,   /* Eq. Visco_lin instead of the harmonic Eq. Viscosity */
-  LBM_GEQ_CAC = 16       /* CAC equilibrium form of Eq. Geq_AC-1            */
+  LBM_GEQ_CAC = 16,      /* CAC equilibrium form of Eq. Geq_AC-1            */
+  LBM_DIV_LOCAL = 32     /* div(u phi) of the latent-heat source taken as
+                          * u.grad(phi) + phi m''' (1/rho_g - 1/rho_l), from
+                          * div(u) of Eq. ConservMasse_ChgtPhase, with the
+                          * production of the previous step (radius-1 form);
+                          * default: the central stencil of Eq. Grad applied
+                          * to u_a phi (radius 2)                            */
 };
+
+/* Collision operator of all three families (Sec. 3, the remark after Eq.
+ * LBE: TRT and MRT reach lower mobility and higher Peclet numbers than BGK).
+ *   BGK: one rate per family, omega = 1/(tau + 1/2), tau = diffusivity/c_s^2.
+ *   TRT: the parts of (pop - eq + S/2) symmetric and antisymmetric under
+ *        c -> -c relax with omega+ and omega-.  The rate of the transport
+ *        coefficient is the BGK rate (omega+ for f: viscosity; omega- for g
+ *        and s: mobility, diffusivity); the other follows from the magic
+ *        parameter Lambda = (1/omega+ - 1/2)(1/omega- - 1/2) (trt_lambda).
+ *   MRT: (pop - eq + S/2) is relaxed in an orthogonal moment basis (D2Q9:
+ *        rho, e, eps, jx, qx, jy, qy, pxx, pxy; D3Q7: 1, cx, cy, cz,
+ *        7c^2 - 6, 2cx^2 - cy^2 - cz^2, cy^2 - cz^2).  The transport moments
+ *        relax at the BGK rate (pxx, pxy for f; jx, jy(, jz) for g and s);
+ *        the others at mrt_rates[family] = {s_e, s_eps, s_q, s_p}: the
+ *        zeroth moment at s_e, j of f at s_q, pxx/pxy of g and s (and the two
+ *        D3Q7 second-order moments) at s_p.  Not built for D3Q19. */
+enum { LBM_COLL_BGK = 0, LBM_COLL_TRT = 1, LBM_COLL_MRT = 2 };
+
+/* Directional derivatives entering Eq. Grad for grad(phi) (normal, surface
+ * tension, grad rho; Sec. 3.4): central (Eq. DerivDirec_Grad), or the
+ * first- or second-order biased (upwind) differences the paper lists after
+ * Eq. Laplacian.  The Laplacian and div(u phi) keep the central form.
+ * BIASED2 reaches two nodes along each direction (2-D only). */
+enum { LBM_GRAD_CENTRAL = 0, LBM_GRAD_BIASED1 = 1, LBM_GRAD_BIASED2 = 2 };
 
 /* dtype of caller field arrays */
 enum { LBM_DT_F32 = 0, LBM_DT_F64 = 1 };
@@ -107,6 +137,14 @@ typedef struct {
   double phi_wall[3][2];         /* [axis][lo, hi] anti-bounce-back phi       */
   double T_wall[3][2];           /* [axis][lo, hi] anti-bounce-back T         */
   double eps_n;                  /* n = grad phi / sqrt(|grad phi|^2 + eps_n^2) (0 -> 1e-3) */
+  int32_t collision;             /* LBM_COLL_*                                 */
+  double trt_lambda[3];          /* TRT magic parameter of f, g, s (0 -> 1/4)  */
+  double mrt_rates[3][4];        /* MRT free rates of f, g, s: s_e, s_eps, s_q, s_p, each in (0, 2) */
+  int32_t grad_scheme;           /* LBM_GRAD_*                                 */
+  int32_t check_every;           /* > 0: lbm_step checks the fields for non-finite
+                                  * values every check_every steps (FP64
+                                  * reduction; synchronises) and returns
+                                  * LBM_E_UNSTABLE at the first failure     */
 } lbm_params;
 
 /* Bytes of device workspace lbm_create needs for these parameters
@@ -128,19 +166,24 @@ lbm_status lbm_create(const lbm_params* prm, void* dev_workspace, size_t bytes,
  * the optional u0 ([3][nz][ny][nx], NULL = 0) and p0 (NULL = 0): every
  * population is set to its equilibrium minus half its source at these
  * fields, so that the moments of the first step return them exactly.
- * T0 is ignored without LBM_HEAT.  dtype = LBM_DT_F32 or LBM_DT_F64. */
+ * T0 is ignored without LBM_HEAT.  dtype = LBM_DT_F32 or LBM_DT_F64.
+ * Discards a recorded adjoint tape. */
 lbm_status lbm_init_fields(lbm_ctx* ctx, const void* phi0, const void* T0,
                            const void* u0, const void* p0, int32_t dtype);
 
 /* Per-node wall temperature on face (axis, side): a device array over the
  * other two axes in [..][..] C order (2-D y wall: nx values; 3-D z wall:
- * [ny][nx]).  Takes effect for the following steps. */
+ * [ny][nx]).  Takes effect for the following steps; discards a recorded
+ * adjoint tape (its recomputation would use the new wall values). */
 lbm_status lbm_set_wall_T(lbm_ctx* ctx, int32_t axis, int32_t side,
                           const void* dev_face, int32_t dtype);
 
 /* Advance nsteps time steps (asynchronous, stream-ordered).  Each step is
  * one fused pass: pull streaming with wall links, moments, stencils,
- * closures, equilibria, sources and BGK collision of f, g and s. */
+ * closures, equilibria, sources and collision of f, g and s.  With
+ * check_every > 0 the call synchronises every check_every steps and returns
+ * LBM_E_UNSTABLE (after the step that produced them) if any node's phi, T,
+ * u or p is non-finite; lbm_get_step then tells how far it got. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
 /* Write the macroscopic fields selected by `mask` (LBM_FIELD_* bits) at the
@@ -158,7 +201,8 @@ lbm_status lbm_diagnostics(lbm_ctx* ctx, double out[5]);
 
 /* Checkpoint / resume: the raw state (populations, lagged phi and q, and
  * T_ref for 16-bit storage) as an opaque byte blob of lbm_state_size bytes,
- * copied device-to-device. */
+ * copied device-to-device.  lbm_set_state discards a recorded adjoint tape
+ * and resets the step count to 0. */
 lbm_status lbm_state_size(const lbm_ctx* ctx, size_t* bytes);
 lbm_status lbm_get_state(lbm_ctx* ctx, void* dev_out, size_t bytes);
 lbm_status lbm_set_state(lbm_ctx* ctx, const void* dev_in, size_t bytes);
@@ -169,36 +213,50 @@ lbm_status lbm_get_step(const lbm_ctx* ctx, int64_t* out);
 /* Wait for all work queued on the context's stream; reports HIP errors. */
 lbm_status lbm_sync(lbm_ctx* ctx);
 
-/* ---- Adjoint (2-D, FP32 or FP64 storage, LBM_NS | LBM_HEAT, at most one
- * walled axis).  Gradients of a loss L(phi^N) of the final phase field with
- * respect to the initial phase field phi0, the initial temperature T0 and a
+/* ---- Adjoint (2-D, FP32 or FP64 storage, LBM_NS | LBM_HEAT, BGK collision,
+ * central gradients, at most one walled axis).  Gradients of a loss
+ * L(phi^N, T^N) of the final phase field and temperature with respect to
+ * the initial phase field phi0, the initial temperature T0 and a
  * wall-temperature row, by a hand-written reverse sweep of the fused step
  * (transposed node Jacobian, transposed stencils, transposed pull gather;
- * the anti-bounce-back links of Sec. 3.3 carry T_w linearly).  Memory uses
- * sqrt(T) checkpointing: snapshots every ceil(sqrt(N)) steps and a
- * recomputed segment during the reverse sweep. */
+ * the anti-bounce-back links of Sec. 3.3 carry T_w linearly). */
 
-/* Bytes of the tape for nsteps (snapshots plus one segment of states). */
-lbm_status lbm_tape_size(const lbm_ctx* ctx, int64_t nsteps, size_t* bytes);
+/* Checkpointing policy of the tape.  SQRT: snapshots every K = ceil(sqrt(N))
+ * steps plus one recomputed segment of K states (memory O(sqrt N) states,
+ * N - ceil(N/K) recomputed steps).  BINOMIAL is reserved (returns
+ * LBM_E_UNSUPPORTED). */
+enum { LBM_TAPE_SQRT = 0, LBM_TAPE_BINOMIAL = 1 };
 
-/* Advance nsteps from the current state (normally right after
- * lbm_init_fields) while recording the tape in dev_tape (caller-owned,
- * 256-byte aligned, >= lbm_tape_size bytes; borrowed until the next
- * lbm_forward_taped).  Asynchronous. */
-lbm_status lbm_forward_taped(lbm_ctx* ctx, int64_t nsteps, void* dev_tape, size_t bytes);
+/* Bytes of the tape for nsteps under `policy`. */
+lbm_status lbm_tape_size(const lbm_ctx* ctx, int64_t nsteps, int32_t policy, size_t* bytes);
+
+/* Advance nsteps from a freshly initialised state while recording the tape
+ * in dev_tape (caller-owned, 256-byte aligned, >= lbm_tape_size bytes;
+ * borrowed until the next lbm_forward_taped).  The context must be at step
+ * 0 of an lbm_init_fields call with u0 == NULL (the reverse sweep
+ * differentiates that initialisation): otherwise LBM_E_STATE.
+ * Asynchronous. */
+lbm_status lbm_forward_taped(lbm_ctx* ctx, int64_t nsteps, int32_t policy, void* dev_tape,
+                             size_t bytes);
 
 /* Bytes of the scratch workspace lbm_backward needs. */
 lbm_status lbm_adjoint_workspace_size(const lbm_ctx* ctx, size_t* bytes);
 
-/* Reverse sweep over the taped steps.  dev_gphi: dL/dphi^N, device array
- * [ny][nx] of gphi_dtype.  Writes (each nullable) d_phi0 [ny][nx], d_T0
- * [ny][nx] and the gradient of the wall-temperature face (tw_axis, tw_side)
- * (nx values for a y wall) as out_dtype.  The context's current state is
- * left at step N.  Returns LBM_E_STATE if the context stepped after the
- * tape was recorded.  Asynchronous. */
-lbm_status lbm_backward(lbm_ctx* ctx, const void* dev_gphi, int32_t gphi_dtype, void* dev_ws,
-                        size_t ws_bytes, void* d_phi0, void* d_T0, void* d_Twall,
-                        int32_t tw_axis, int32_t tw_side, int32_t out_dtype);
+/* Reverse sweep over the taped steps.  Seeds (device arrays [ny][nx] of
+ * seed_dtype, each nullable, at least one given): g_phi = dL/dphi^N and
+ * g_T = dL/dT^N at the fields lbm_get_fields returns after the taped run.
+ * g_u and g_p (dL/du^N, dL/dp^N) must be NULL: LBM_E_UNSUPPORTED otherwise.
+ * dev_ws: >= lbm_adjoint_workspace_size bytes, 256-byte aligned.  Writes
+ * (each nullable) d_phi0 [ny][nx], d_T0 [ny][nx] and the gradient of the
+ * wall-temperature face (tw_axis, tw_side) (nx values for a y wall) as
+ * out_dtype.  The context's current state is left at step N.  Returns
+ * LBM_E_STATE without a tape, or if the context stepped, was
+ * re-initialised, had its state set or a wall temperature changed after
+ * lbm_forward_taped.  Asynchronous. */
+lbm_status lbm_backward(lbm_ctx* ctx, const void* g_phi, const void* g_T, const void* g_u,
+                        const void* g_p, int32_t seed_dtype, void* dev_ws, size_t ws_bytes,
+                        void* d_phi0, void* d_T0, void* d_Twall, int32_t tw_axis,
+                        int32_t tw_side, int32_t out_dtype);
 
 void lbm_destroy(lbm_ctx* ctx);
 

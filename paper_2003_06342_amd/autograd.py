@@ -2,9 +2,10 @@
 
 ``LBMRun.apply(phi0, Tw, prm, T0, nsteps, storage)`` runs the 2-D film step
 nsteps times from (phi0, T0) with the wall-temperature row Tw on the
-heated floor (face y = 0) and returns phi^N; its backward calls the
-library's reverse sweep (sqrt(T) checkpointing) and returns dL/dphi0 and
-dL/dTw.  Every operation runs in liblbm.so; torch only holds the tensors.
+heated floor (face y = 0) and returns (phi^N, T^N); its backward calls the
+library's reverse sweep (sqrt(T) checkpointing) with the incoming
+dL/dphi^N and dL/dT^N and returns dL/dphi0 and dL/dTw.  Every operation
+runs in liblbm.so; torch only holds the tensors.
 """
 from __future__ import annotations
 
@@ -20,13 +21,17 @@ class LBMRun(torch.autograd.Function):
         sim.set_wall_T(1, 0, Tw.detach())
         sim.init(phi0.detach(), T0)
         sim.forward_taped(int(nsteps))
-        phiN = sim.fields(("phi",))["phi"][0].clone()
+        f = sim.fields(("phi", "T"))
+        phiN = f["phi"][0].clone()
+        TN = f["T"][0].clone()
         ctx.sim = sim
-        return phiN.to(phi0.dtype)
+        return phiN.to(phi0.dtype), TN.to(phi0.dtype)
 
     @staticmethod
-    def backward(ctx, gphi):
-        g = ctx.sim.backward(gphi.detach().to(torch.float64), tw_face=(1, 0))
+    def backward(ctx, gphi, gT):
+        g = ctx.sim.backward(None if gphi is None else gphi.detach().to(torch.float64),
+                             tw_face=(1, 0),
+                             gT=None if gT is None else gT.detach().to(torch.float64))
         ctx.sim.close()
         dphi0 = g["phi0"].reshape(1, *g["phi0"].shape)
         return dphi0, g["Tw"], None, None, None, None

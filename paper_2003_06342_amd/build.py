@@ -1,8 +1,7 @@
 """Build the HIP library liblbm.so for gfx950 in-tree.
 
 Compiles every csrc/*.hip translation unit with hipcc and links one shared
-library next to this file; then the measurement probe libstream_probe.so
-(probe/stream_probe.hip), which bench.py times beside the step.  Packed FP32 instructions are disabled for the
+library next to this file.  Packed FP32 instructions are disabled for the
 device code (-packed-fp32-ops); hipcc's host pass warns that it does not
 know that target feature, which is harmless.
 """
@@ -57,23 +56,19 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, OUT)
-    build_probe(cc)
     return OUT
 
 
-PROBE_SRC = os.path.join(HERE, "probe", "stream_probe.hip")
-PROBE_OUT = os.path.join(HERE, "libstream_probe.so")
-
-
-def build_probe(cc: str) -> str:
-    """The measurement probe bench.py times beside the step (its own library:
-    it is not part of the method's C ABI)."""
-    tmp = PROBE_OUT + ".tmp"
-    r = subprocess.run([cc, *FLAGS, "-shared", PROBE_SRC, "-o", tmp], capture_output=True, text=True)
+def build_shared(src: str, out: str) -> str:
+    """Compile one stand-alone .hip file into a shared library with the
+    library's flags (used for bench.py's measurement probes)."""
+    cc = hipcc()
+    tmp = out + ".tmp"
+    r = subprocess.run([cc, *FLAGS, "-shared", src, "-o", tmp], capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {PROBE_SRC}:\n{r.stderr}")
-    os.replace(tmp, PROBE_OUT)
-    return PROBE_OUT
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -76,6 +76,9 @@ struct lbm_ctx {
   size_t tape_bytes;
   int64_t tape_n, tape_k, tape_nsnap, tape_end_step;
   int tape_ready;
+  // the current state is step `step` of an lbm_init_fields call with u0 ==
+  // NULL (the initialisation the reverse sweep differentiates)
+  int fresh_init;
 };
 
 namespace {
@@ -116,6 +119,29 @@ lbm_status validate(const lbm_params* p) {
   if (p->A_coef < 0) return fail(LBM_E_INVAL, "A_coef must be >= 0");
   if (!(p->sigma >= 0)) return fail(LBM_E_INVAL, "sigma must be >= 0");
   if ((long long)p->nx * p->ny * p->nz > (1LL << 31)) return fail(LBM_E_INVAL, "grid too large");
+  if (p->collision < LBM_COLL_BGK || p->collision > LBM_COLL_MRT)
+    return fail(LBM_E_INVAL, "unknown collision %d", p->collision);
+  if (p->collision == LBM_COLL_TRT)
+    for (int k = 0; k < 3; ++k)
+      if (!(p->trt_lambda[k] >= 0) || !std::isfinite(p->trt_lambda[k]))
+        return fail(LBM_E_INVAL, "trt_lambda[%d] must be finite and >= 0 (0 -> 1/4)", k);
+  if (p->collision == LBM_COLL_MRT) {
+    if (p->dim == 3 && (p->flags & LBM_NS))
+      return fail(LBM_E_UNSUPPORTED, "MRT is built for D2Q9 and D3Q7 (not D3Q19)");
+    for (int k = 0; k < 3; ++k)
+      for (int r = 0; r < 4; ++r)
+        if (!(p->mrt_rates[k][r] > 0 && p->mrt_rates[k][r] < 2))
+          return fail(LBM_E_INVAL, "mrt_rates[%d][%d] must lie in (0, 2)", k, r);
+  }
+  if (p->grad_scheme < LBM_GRAD_CENTRAL || p->grad_scheme > LBM_GRAD_BIASED2)
+    return fail(LBM_E_INVAL, "unknown grad_scheme %d", p->grad_scheme);
+  if (p->grad_scheme == LBM_GRAD_BIASED2) {
+    if (p->dim != 2) return fail(LBM_E_UNSUPPORTED, "LBM_GRAD_BIASED2 is built for 2-D");
+    // the 3-node ghost layer mirrors the third node from the wall
+    if ((p->bc[0] == LBM_BC_WALL && p->nx < 3) || (p->bc[1] == LBM_BC_WALL && p->ny < 3))
+      return fail(LBM_E_INVAL, "LBM_GRAD_BIASED2 needs at least 3 nodes along a walled axis");
+  }
+  if (p->check_every < 0) return fail(LBM_E_INVAL, "check_every must be >= 0");
   if (p->dim == 2) {
     // the 2-D kernel addresses each population family with 32-bit byte offsets
     const long long px = (p->nx + 63) / 64 * 64;
@@ -211,6 +237,13 @@ KArgs<Real, Store> make_args(const lbm_ctx* c) {
   a.visc_linear = (p.flags & LBM_VISC_LINEAR) ? 1 : 0;
   a.geq_cac = (p.flags & LBM_GEQ_CAC) ? 1 : 0;
   a.phase_change = (p.flags & LBM_PHASE_CHANGE) ? 1 : 0;
+  a.div_local = (p.flags & LBM_DIV_LOCAL) ? 1 : 0;
+  a.coll = p.collision;
+  for (int k = 0; k < 3; ++k) {
+    a.lam[k] = (Real)(p.trt_lambda[k] > 0 ? p.trt_lambda[k] : 0.25);
+    for (int r = 0; r < 4; ++r) a.mrt[k][r] = (Real)p.mrt_rates[k][r];
+  }
+  a.grad_scheme = p.grad_scheme;
   const int cur = c->cur;
   a.A = (const Store*)c->pops[cur];
   a.B = (Store*)c->pops[1 - cur];
@@ -394,6 +427,8 @@ lbm_status lbm_init_fields(lbm_ctx* c, const void* phi0, const void* T0, const v
   c->cur = 0;
   c->step = 0;
   c->initialized = 1;
+  c->tape_ready = 0;
+  c->fresh_init = u0 == nullptr;
   return hip_check(e, "lbm_init_fields");
 }
 
@@ -405,25 +440,10 @@ lbm_status lbm_set_wall_T(lbm_ctx* c, int32_t axis, int32_t side, const void* fa
   if (dtype != LBM_DT_F32 && dtype != LBM_DT_F64) return fail(LBM_E_INVAL, "bad dtype");
   const int n[3] = {c->prm.nx, c->prm.ny, c->prm.nz};
   const long long cnt = (long long)n[0] * n[1] * n[2] / n[axis];
+  c->tape_ready = 0;   // a recorded tape would be recomputed with the new wall values
   hipLaunchKernelGGL(k_convert, dim3((cnt + 255) / 256), dim3(256), 0, c->stream, c->tw[axis][side],
                      c->prm.storage == LBM_ST_F64 ? 1 : 0, face, dtype == LBM_DT_F64 ? 1 : 0, cnt);
   return hip_check(hipGetLastError(), "lbm_set_wall_T");
-}
-
-lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
-  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
-  if (!c->initialized) return fail(LBM_E_STATE, "lbm_step before lbm_init_fields / lbm_set_state");
-  if (nsteps < 0) return fail(LBM_E_INVAL, "nsteps < 0");
-  for (int64_t k = 0; k < nsteps; ++k) {
-    hipError_t e = dispatch(c, [&](auto a) {
-      return c->prm.dim == 2 ? launch_step2d(a, c->ns, c->heat, MODE_STEP, c->stream)
-                             : launch_step3d(a, c->ns, c->heat, MODE_STEP, c->stream);
-    });
-    if (e != hipSuccess) return hip_check(e, "lbm_step");
-    c->cur = 1 - c->cur;
-    ++c->step;
-  }
-  return LBM_OK;
 }
 
 static lbm_status run_macro(lbm_ctx* c, uint32_t mask, void* out, int f64, double* partials) {
@@ -436,6 +456,43 @@ static lbm_status run_macro(lbm_ctx* c, uint32_t mask, void* out, int f64, doubl
                            : launch_step3d(a, c->ns, c->heat, MODE_MACRO, c->stream);
   });
   return hip_check(e, "macro pass");
+}
+
+// FP64 sums of the current fields into r[NPART] (host): sum phi, sum T,
+// sum phi_prev, max |u|, count of non-finite nodes.  Synchronises.
+static lbm_status reduce_fields(lbm_ctx* c, double* r) {
+  lbm_status s = run_macro(c, 0u, nullptr, 0, c->partials);
+  if (s != LBM_OK) return s;
+  s = hip_check(launch_reduce(c->partials, c->L.nblocks, c->red, c->stream), "reduce");
+  if (s != LBM_OK) return s;
+  s = hip_check(hipMemcpyAsync(r, c->red, NPART * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                "copy");
+  if (s != LBM_OK) return s;
+  return hip_check(hipStreamSynchronize(c->stream), "reduce_fields");
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
+  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  if (!c->initialized) return fail(LBM_E_STATE, "lbm_step before lbm_init_fields / lbm_set_state");
+  if (nsteps < 0) return fail(LBM_E_INVAL, "nsteps < 0");
+  const int every = c->prm.check_every;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    hipError_t e = dispatch(c, [&](auto a) {
+      return c->prm.dim == 2 ? launch_step2d(a, c->ns, c->heat, MODE_STEP, c->stream)
+                             : launch_step3d(a, c->ns, c->heat, MODE_STEP, c->stream);
+    });
+    if (e != hipSuccess) return hip_check(e, "lbm_step");
+    c->cur = 1 - c->cur;
+    ++c->step;
+    if (every > 0 && c->step % every == 0) {
+      double r[NPART];
+      lbm_status s = reduce_fields(c, r);
+      if (s != LBM_OK) return s;
+      if (r[4] != 0)
+        return fail(LBM_E_UNSTABLE, "%.0f non-finite nodes after step %lld", r[4], (long long)c->step);
+    }
+  }
+  return LBM_OK;
 }
 
 lbm_status lbm_get_fields(lbm_ctx* c, uint32_t mask, void* out, int32_t dtype) {
@@ -451,14 +508,8 @@ lbm_status lbm_get_fields(lbm_ctx* c, uint32_t mask, void* out, int32_t dtype) {
 lbm_status lbm_diagnostics(lbm_ctx* c, double out[5]) {
   if (!c || !out) return fail(LBM_E_INVAL, "NULL argument");
   if (!c->initialized) return fail(LBM_E_STATE, "lbm_diagnostics before initialisation");
-  lbm_status s = run_macro(c, 0u, nullptr, 0, c->partials);
-  if (s != LBM_OK) return s;
-  s = hip_check(launch_reduce(c->partials, c->L.nblocks, c->red, c->stream), "reduce");
-  if (s != LBM_OK) return s;
   double r[NPART];
-  s = hip_check(hipMemcpyAsync(r, c->red, sizeof r, hipMemcpyDeviceToHost, c->stream), "copy");
-  if (s != LBM_OK) return s;
-  s = hip_check(hipStreamSynchronize(c->stream), "lbm_diagnostics");
+  lbm_status s = reduce_fields(c, r);
   if (s != LBM_OK) return s;
   const double N = (double)c->prm.nx * c->prm.ny * c->prm.nz;
   const double Lcp = c->heat ? c->prm.L_over_cp : 0.0;
@@ -511,6 +562,8 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* in, size_t bytes) {
                        hipMemcpyDeviceToDevice, c->stream);
   c->initialized = 1;
   c->step = 0;
+  c->tape_ready = 0;
+  c->fresh_init = 0;
   return hip_check(e, "lbm_set_state");
 }
 
@@ -548,6 +601,10 @@ lbm_status adjoint_supported(const lbm_ctx* c) {
   if (!c->ns || !c->heat) return fail(LBM_E_UNSUPPORTED, "adjoint needs LBM_NS | LBM_HEAT");
   if (p.bc[0] == LBM_BC_WALL && p.bc[1] == LBM_BC_WALL)
     return fail(LBM_E_UNSUPPORTED, "adjoint supports at most one walled axis");
+  if (p.collision != LBM_COLL_BGK) return fail(LBM_E_UNSUPPORTED, "adjoint is built for BGK collision");
+  if (p.grad_scheme != LBM_GRAD_CENTRAL)
+    return fail(LBM_E_UNSUPPORTED, "adjoint is built for central gradients");
+  if (p.flags & LBM_DIV_LOCAL) return fail(LBM_E_UNSUPPORTED, "adjoint is built without LBM_DIV_LOCAL");
   return LBM_OK;
 }
 
@@ -575,15 +632,15 @@ size_t adj_ws_bytes(const lbm_ctx* c) {
   const size_t R = c->prm.storage == LBM_ST_F64 ? 8 : 4;
   const size_t plane = align256((size_t)c->L.slab * R);
   const size_t field = align256((size_t)c->prm.nx * c->prm.ny * R);
-  size_t tot = (27 + 2 + 27 + LL_N + 3) * plane + 3 * field;
+  size_t tot = (27 + 2 + 27 + LL_N + 3) * plane + 4 * field;
   for (int a = 0; a < 2; ++a)
     if (c->prm.bc[a] == LBM_BC_WALL) tot += 2 * align256((size_t)(a == 0 ? c->prm.ny : c->prm.nx) * R);
   return tot;
 }
 
 template <class Real>
-lbm_status backward_t(lbm_ctx* c, const void* gphi, int32_t gdt, void* ws, void* d_phi0, void* d_T0,
-                      void* d_Tw, int32_t tw_axis, int32_t tw_side, int32_t odt) {
+lbm_status backward_t(lbm_ctx* c, const void* gphi, const void* gT, int32_t gdt, void* ws, void* d_phi0,
+                      void* d_T0, void* d_Tw, int32_t tw_axis, int32_t tw_side, int32_t odt) {
   const size_t R = sizeof(Real);
   const long long nxy = (long long)c->prm.nx * c->prm.ny;
   const size_t plane = align256((size_t)c->L.slab * R);
@@ -599,6 +656,7 @@ lbm_status backward_t(lbm_ctx* c, const void* gphi, int32_t gdt, void* ws, void*
   b.fux = (Real*)p;      p += plane;
   b.fuy = (Real*)p;      p += plane;
   Real* seed = (Real*)p; p += field;
+  Real* seedT = (Real*)p; p += field;
   Real* dphi = (Real*)p; p += field;
   Real* dT0 = (Real*)p;  p += field;
   for (int a = 0; a < 2; ++a)
@@ -619,13 +677,20 @@ lbm_status backward_t(lbm_ctx* c, const void* gphi, int32_t gdt, void* ws, void*
   char* snaps = c->tape;
   char* seg = c->tape + (size_t)c->tape_nsnap * ss;
   hipError_t e;
-  // seed at the final state (the context's current state)
-  hipLaunchKernelGGL(k_convert, dim3((nxy + 255) / 256), dim3(256), 0, c->stream, (void*)seed, f64,
-                     gphi, gdt == LBM_DT_F64 ? 1 : 0, nxy);
+  // seed at the final state (the context's current state): phi^N and T^N
+  // as the fields pass computes them, transposed onto lambda of X^N
+  const int gdt64 = gdt == LBM_DT_F64 ? 1 : 0;
+  if (gphi)
+    hipLaunchKernelGGL(k_convert, dim3((nxy + 255) / 256), dim3(256), 0, c->stream, (void*)seed, f64,
+                       gphi, gdt64, nxy);
+  if (gT)
+    hipLaunchKernelGGL(k_convert, dim3((nxy + 255) / 256), dim3(256), 0, c->stream, (void*)seedT, f64,
+                       gT, gdt64, nxy);
   {
     KArgs<Real, Real> a = make_args<Real, Real>(c);
-    e = launch_adj_seed2d(a, b, seed, c->stream);
+    e = launch_adj_seed2d(a, b, gphi ? seed : nullptr, gT ? seedT : nullptr, c->stream);
     if (e != hipSuccess) return hip_check(e, "adjoint seed");
+    std::swap(b.lA, b.lP);   // the seed left lambda_A of X^N in lP
   }
   const int64_t N = c->tape_n, K = c->tape_k;
   for (int64_t s = c->tape_nsnap - 1; s >= 0; --s) {
@@ -670,22 +735,28 @@ lbm_status backward_t(lbm_ctx* c, const void* gphi, int32_t gdt, void* ws, void*
 
 extern "C" {
 
-lbm_status lbm_tape_size(const lbm_ctx* c, int64_t nsteps, size_t* bytes) {
+lbm_status lbm_tape_size(const lbm_ctx* c, int64_t nsteps, int32_t policy, size_t* bytes) {
   if (!c || !bytes) return fail(LBM_E_INVAL, "NULL argument");
   if (nsteps < 1) return fail(LBM_E_INVAL, "nsteps must be >= 1");
+  if (policy == LBM_TAPE_BINOMIAL) return fail(LBM_E_UNSUPPORTED, "LBM_TAPE_BINOMIAL is not built");
+  if (policy != LBM_TAPE_SQRT) return fail(LBM_E_INVAL, "unknown tape policy %d", policy);
   int64_t k, ns;
   tape_shape(nsteps, k, ns);
   *bytes = (size_t)(ns + k) * state_bytes(c);
   return LBM_OK;
 }
 
-lbm_status lbm_forward_taped(lbm_ctx* c, int64_t nsteps, void* tape, size_t bytes) {
+lbm_status lbm_forward_taped(lbm_ctx* c, int64_t nsteps, int32_t policy, void* tape, size_t bytes) {
   if (!c || !tape) return fail(LBM_E_INVAL, "NULL argument");
   lbm_status st = adjoint_supported(c);
   if (st != LBM_OK) return st;
   if (!c->initialized) return fail(LBM_E_STATE, "lbm_forward_taped before initialisation");
+  if (!c->fresh_init || c->step != 0)
+    return fail(LBM_E_STATE,
+                "lbm_forward_taped needs step 0 of lbm_init_fields with u0 == NULL (the reverse sweep "
+                "differentiates that initialisation)");
   size_t need;
-  st = lbm_tape_size(c, nsteps, &need);
+  st = lbm_tape_size(c, nsteps, policy, &need);
   if (st != LBM_OK) return st;
   if (bytes < need) return fail(LBM_E_NOMEM, "tape has %zu bytes, needs %zu", bytes, need);
   if (((uintptr_t)tape & 255) != 0) return fail(LBM_E_INVAL, "tape must be 256-byte aligned");
@@ -703,6 +774,7 @@ lbm_status lbm_forward_taped(lbm_ctx* c, int64_t nsteps, void* tape, size_t byte
                          c->stream);
     return e;
   };
+  c->tape_ready = 0;
   hipError_t e = snap(0);
   if (e != hipSuccess) return hip_check(e, "tape snapshot");
   for (int64_t n = 1; n <= nsteps; ++n) {
@@ -731,24 +803,30 @@ lbm_status lbm_adjoint_workspace_size(const lbm_ctx* c, size_t* bytes) {
   return LBM_OK;
 }
 
-lbm_status lbm_backward(lbm_ctx* c, const void* dev_gphi, int32_t gphi_dtype, void* dev_ws,
-                        size_t ws_bytes, void* d_phi0, void* d_T0, void* d_Twall, int32_t tw_axis,
-                        int32_t tw_side, int32_t out_dtype) {
-  if (!c || !dev_gphi || !dev_ws) return fail(LBM_E_INVAL, "NULL argument");
+lbm_status lbm_backward(lbm_ctx* c, const void* g_phi, const void* g_T, const void* g_u,
+                        const void* g_p, int32_t seed_dtype, void* dev_ws, size_t ws_bytes,
+                        void* d_phi0, void* d_T0, void* d_Twall, int32_t tw_axis, int32_t tw_side,
+                        int32_t out_dtype) {
+  if (!c || !dev_ws) return fail(LBM_E_INVAL, "NULL argument");
+  if (!g_phi && !g_T) return fail(LBM_E_INVAL, "no seed: g_phi and g_T are both NULL");
+  if (g_u || g_p) return fail(LBM_E_UNSUPPORTED, "seeds on u^N and p^N are not built");
   lbm_status st = adjoint_supported(c);
   if (st != LBM_OK) return st;
-  if (!c->tape_ready) return fail(LBM_E_STATE, "lbm_backward without lbm_forward_taped");
+  if (!c->tape_ready) return fail(LBM_E_STATE, "lbm_backward without a current lbm_forward_taped tape");
   if (c->step != c->tape_end_step)
     return fail(LBM_E_STATE, "the context stepped after lbm_forward_taped");
   if (ws_bytes < adj_ws_bytes(c)) return fail(LBM_E_NOMEM, "adjoint workspace too small");
   if (((uintptr_t)dev_ws & 255) != 0) return fail(LBM_E_INVAL, "workspace must be 256-byte aligned");
-  if ((gphi_dtype != LBM_DT_F32 && gphi_dtype != LBM_DT_F64) ||
+  if ((seed_dtype != LBM_DT_F32 && seed_dtype != LBM_DT_F64) ||
       (out_dtype != LBM_DT_F32 && out_dtype != LBM_DT_F64))
     return fail(LBM_E_INVAL, "bad dtype");
+  if (d_Twall && (tw_axis < 0 || tw_axis > 1 || tw_side < 0 || tw_side > 1 ||
+                  c->prm.bc[tw_axis] != LBM_BC_WALL))
+    return fail(LBM_E_INVAL, "wall face (%d, %d) is not a walled face", tw_axis, tw_side);
   if (c->prm.storage == LBM_ST_F64)
-    return backward_t<double>(c, dev_gphi, gphi_dtype, dev_ws, d_phi0, d_T0, d_Twall, tw_axis, tw_side,
+    return backward_t<double>(c, g_phi, g_T, seed_dtype, dev_ws, d_phi0, d_T0, d_Twall, tw_axis, tw_side,
                               out_dtype);
-  return backward_t<float>(c, dev_gphi, gphi_dtype, dev_ws, d_phi0, d_T0, d_Twall, tw_axis, tw_side,
+  return backward_t<float>(c, g_phi, g_T, seed_dtype, dev_ws, d_phi0, d_T0, d_Twall, tw_axis, tw_side,
                            out_dtype);
 }
 

@@ -20,7 +20,8 @@
 // was read from, in a second buffer that becomes lambda_A of the earlier
 // state; anti-bounce-back links of s add 2 w_i lambda to the wall-temperature
 // gradient (K_A).  K_C alone (the phi transpose from node fields in memory)
-// serves the initial-condition step; K_D (push) remains for the seed only.
+// serves the initial-condition step.  The seed (a loss of phi^N and T^N)
+// is a local kernel of its own followed by K_BC.
 // Supports at most one walled axis (ghost corners are not differentiated).
 #include "lbm_adjoint.h"
 #include "lbm_adjargs.h"
@@ -407,54 +408,63 @@ __global__ __launch_bounds__(TX2 * TY) void k_adj_uphi2d(const KArgs<Real, Real>
 }
 
 // ---------------------------------------------------------------------------
-// K_D: transpose of the pull gather
+// Seed: a loss of the final fields with dL/dphi^N = gphi and dL/dT^N = gT
+// (fields [ny][nx] of Real, each nullable), at the fields of the state X^N
+// as the fields pass computes them:
+//   phi^N = sum g (pulled) + q_prev / 2,
+//   T^N   = sum s (pulled) - (L/Cp)/2 [phi^N - phi_prev + div(u^N phi^N)].
+// This kernel recomputes phi and u on the tile in LDS (as the forward), sends
+// gT to the pulled s (at the slots they were read from; anti-bounce-back
+// links add 2 w_i gT to the wall-temperature gradient) and leaves the node
+// adjoints of phi and D for the u / phi transposes (K_BC), which carry them
+// to the pulled f and g and to q_prev.
 // ---------------------------------------------------------------------------
-template <class Real>
-__global__ __launch_bounds__(256) void k_adj_push2d(const KArgs<Real, Real> a, const AdjArgs<Real> b) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= a.nx || y >= a.ny) return;
-  const unsigned node = (unsigned)(y * a.px + x);
-  Real tw[2][2] = {{0, 0}, {0, 0}};
-  for (int fam = 0; fam < 3; ++fam) {
-    for (int j = 0; j < 9; ++j) {
-      const int cx = D2Q9::cx(j), cy = D2Q9::cy(j);
-      int yx = x + cx, yy = y + cy;
-      const bool oy = cy != 0 && a.wall[1] && (yy < 0 || yy >= a.ny);
-      const bool ox = cx != 0 && !oy && a.wall[0] && (yx < 0 || yx >= a.nx);
-      Real v;
-      if (oy || ox) {
-        const int i = D2Q9::opp(j);
-        const Real lp = b.lP[(size_t)(fam * 9 + i) * a.slab + node];
-        v = fam == 0 ? lp : -lp;
-        if (fam == 2) {
-          const int ax = oy ? 1 : 0;
-          const int side = oy ? (yy < 0 ? 0 : 1) : (yx < 0 ? 0 : 1);
-          tw[ax][side] += (Real)2 * (Real)D2Q9::w(i) * lp;
-        }
-      } else {
-        if (!a.wall[0]) yx = wrap1(yx, a.nx);
-        if (!a.wall[1]) yy = wrap1(yy, a.ny);
-        v = b.lP[(size_t)(fam * 9 + j) * a.slab + (unsigned)(yy * a.px + yx)];
+template <class Real, int TY>
+__global__ __launch_bounds__(Tile2<TY>::NT) void k_adj_seed_local2d(const KArgs<Real, Real> a,
+                                                                   const AdjArgs<Real> b,
+                                                                   const Real* gphi, const Real* gT) {
+  __shared__ Real sphi[Tile2<TY>::R1Y][R1X];
+  __shared__ Real sux[Tile2<TY>::R2Y][R2X];
+  __shared__ Real suy[Tile2<TY>::R2Y][R2X];
+  const int tiles_x = (a.nx + TX2 - 1) / TX2;
+  const int t = blockIdx.x;
+  const int x0 = (t % tiles_x) * TX2, y0 = (t / tiles_x) * TY;
+  stage2d<Real, Real, true, true, false, TY>(a, sphi, sux, suy, x0, y0);
+  const int tid = threadIdx.x, lx = tid % TX2;
+  for (int r = tid / TX2; r < TY; r += Tile2<TY>::NT / TX2) {
+    const int x = x0 + lx, y = y0 + r;
+    if (x >= a.nx || y >= a.ny) continue;
+    const unsigned node = (unsigned)(y * a.px + x);
+    const unsigned fidx = (unsigned)(y * a.nx + x);
+    const Real gp = gphi ? gphi[fidx] : (Real)0;
+    const Real gt = gT ? gT[fidx] : (Real)0;
+    const Real hl = (Real)0.5 * b.nc.Lcp * gt;
+    Real tw[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+    for (int fam = 0; fam < 3; ++fam)
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        Real sg;
+        int wax, wsd;
+        const size_t slot = pull_slot(a, fam, i, x, y, sg, wax, wsd);
+        b.lP[slot] = fam == 2 ? sg * gt : (Real)0;
+        if (fam == 2 && wax >= 0) tw[wax][wsd] += (Real)2 * (Real)D2Q9::w(i) * gt;
       }
-      b.lA[(size_t)(fam * 9 + j) * a.slab + node] = v;
-    }
+    for (int ax = 0; ax < 2; ++ax)
+      for (int sd = 0; sd < 2; ++sd)
+        if (b.lTw[ax][sd] && tw[ax][sd] != (Real)0) b.lTw[ax][sd][ax == 1 ? x : y] += tw[ax][sd];
+    b.lloc[(size_t)LL_PHI * a.slab + node] = gp - hl;
+    b.lloc[(size_t)LL_GX * a.slab + node] = 0;
+    b.lloc[(size_t)LL_GY * a.slab + node] = 0;
+    b.lloc[(size_t)LL_LAP * a.slab + node] = 0;
+    b.lloc[(size_t)LL_UX * a.slab + node] = 0;
+    b.lloc[(size_t)LL_UY * a.slab + node] = 0;
+    b.lloc[(size_t)LL_D * a.slab + node] = -hl;
+    b.lphip[node] = hl;
+    b.fphi[node] = sphi[r + 2][lx + 2];
+    b.fux[node] = sux[r + 1][lx + 1];
+    b.fuy[node] = suy[r + 1][lx + 1];
   }
-  for (int ax = 0; ax < 2; ++ax)
-    for (int side = 0; side < 2; ++side)
-      if (b.lTw[ax][side] && tw[ax][side] != (Real)0) b.lTw[ax][side][ax == 1 ? x : y] += tw[ax][side];
-}
-
-// Seed: loss of the final phase field with dL/dphi^N = gphi (field
-// [ny][nx] of Real).  phi^N = sum g (pulled) + q_prev / 2.
-template <class Real>
-__global__ void k_adj_seed2d(const KArgs<Real, Real> a, const AdjArgs<Real> b, const Real* gphi) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-  if (x >= a.nx || y >= a.ny) return;
-  const unsigned node = (unsigned)(y * a.px + x);
-  const Real gv = gphi[(unsigned)(y * a.nx + x)];
-  for (int i = 0; i < 27; ++i) b.lP[(size_t)i * a.slab + node] = (i >= 9 && i < 18) ? gv : (Real)0;
-  b.lphip[node] = 0;
-  b.lqp[node] = (Real)0.5 * gv;
 }
 
 // Initial-condition adjoint, local part.  The initial state is the pull
@@ -553,9 +563,14 @@ hipError_t launch_adj_step2d_t(const KArgs<Real, Real>& a, const AdjArgs<Real>& 
 
 template <class Real>
 hipError_t launch_adj_seed2d_t(const KArgs<Real, Real>& a, const AdjArgs<Real>& b, const Real* gphi,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_seed2d<Real>, node_grid(a), dim3(256), 0, st, a, b, gphi);
-  hipLaunchKernelGGL(k_adj_push2d<Real>, node_grid(a), dim3(256), 0, st, a, b);
+                               const Real* gT, hipStream_t st) {
+  constexpr int ty = 8;
+  const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + ty - 1) / ty);
+  hipLaunchKernelGGL((k_adj_seed_local2d<Real, ty>), dim3(tiles), dim3(Tile2<ty>::NT), 0, st, a, b,
+                     gphi, gT);
+  constexpr int tyb = 16;
+  const int tiles_b = ((a.nx + TX2 - 1) / TX2) * ((a.ny + tyb - 1) / tyb);
+  hipLaunchKernelGGL((k_adj_uphi2d<Real, tyb>), dim3(tiles_b), dim3(TX2 * tyb), 0, st, a, b);
   return hipGetLastError();
 }
 
@@ -573,8 +588,8 @@ hipError_t launch_adj_init2d_t(const KArgs<Real, Real>& a, const AdjArgs<Real>& 
     return launch_adj_step2d_t<REAL>(a, b, st);                                               \
   }                                                                                           \
   hipError_t launch_adj_seed2d(const KArgs<REAL, REAL>& a, const AdjArgs<REAL>& b,             \
-                               const REAL* g, hipStream_t st) {                               \
-    return launch_adj_seed2d_t<REAL>(a, b, g, st);                                            \
+                               const REAL* g, const REAL* gT, hipStream_t st) {               \
+    return launch_adj_seed2d_t<REAL>(a, b, g, gT, st);                                        \
   }                                                                                           \
   hipError_t launch_adj_init2d(const KArgs<REAL, REAL>& a, const AdjArgs<REAL>& b, REAL* dphi0, \
                                REAL* dT0, hipStream_t st) {                                   \

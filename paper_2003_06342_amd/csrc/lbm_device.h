@@ -162,7 +162,12 @@ struct KArgs {
   Real Lcp, inv_Lcp, T_sat, theta_I, qcoef;   // qcoef = 4 / (A W^2)
   Real omega_g, M_over_cs2g;
   Real prod_fac;          // rho_g (1/rho_g - 1/rho_l): P^f = w rho c_s^2 q prod_fac
-  int visc_linear, geq_cac, phase_change;
+  int visc_linear, geq_cac, phase_change, div_local;
+  // collision (LBM_COLL_*): TRT magic parameters and MRT free rates per family
+  int coll;
+  Real lam[3];
+  Real mrt[3][4];
+  int grad_scheme;        // LBM_GRAD_*
   // macro output (MODE_MACRO): planes of nx*ny*nz
   void* out;
   int out_f64;

@@ -83,7 +83,7 @@ template <class Real> struct AdjArgs;
   hipError_t launch_adj_step2d(const KArgs<REAL, REAL>& a, const AdjArgs<REAL>& b,             \
                                hipStream_t st);                                               \
   hipError_t launch_adj_seed2d(const KArgs<REAL, REAL>& a, const AdjArgs<REAL>& b,             \
-                               const REAL* g, hipStream_t st);                                \
+                               const REAL* g, const REAL* gT, hipStream_t st);                \
   hipError_t launch_adj_init2d(const KArgs<REAL, REAL>& a, const AdjArgs<REAL>& b, REAL* dphi0, \
                                REAL* dT0, hipStream_t st);
 LBM_ADJ_DECL(float)

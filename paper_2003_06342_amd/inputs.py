@@ -46,6 +46,12 @@ _BASE = dict(
     phi_wall=[[0.0, 0.0], [0.0, 0.0], [0.0, 0.0]],
     T_wall=[[0.0, 0.0], [0.0, 0.0], [0.0, 0.0]],
     eps_n=1e-3,
+    div_local=False,
+    collision="bgk",                  # "bgk" | "trt" | "mrt"
+    trt_lambda=[0.25, 0.25, 0.25],    # TRT magic parameter of f, g, s
+    mrt_rates=[[1.0] * 4, [1.0] * 4, [1.0] * 4],   # MRT s_e, s_eps, s_q, s_p of f, g, s
+    grad_scheme="central",            # "central" | "biased1" | "biased2"
+    check_every=0,
 )
 
 

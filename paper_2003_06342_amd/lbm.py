@@ -22,7 +22,11 @@ LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_STATE, LBM_E_UNSTABLE, LBM_E_
 LBM_D2Q9, LBM_D3Q7, LBM_D3Q19 = 9, 7, 19
 ST = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3}
 LBM_BC_PERIODIC, LBM_BC_WALL = 0, 1
-LBM_NS, LBM_HEAT, LBM_PHASE_CHANGE, LBM_VISC_LINEAR, LBM_GEQ_CAC = 1, 2, 4, 8, 16
+LBM_NS, LBM_HEAT, LBM_PHASE_CHANGE, LBM_VISC_LINEAR, LBM_GEQ_CAC, LBM_DIV_LOCAL = \
+    1, 2, 4, 8, 16, 32
+COLL = {"bgk": 0, "trt": 1, "mrt": 2}
+GRAD = {"central": 0, "biased1": 1, "biased2": 2}
+LBM_TAPE_SQRT, LBM_TAPE_BINOMIAL = 0, 1
 LBM_DT_F32, LBM_DT_F64 = 0, 1
 FIELDS = ["phi", "p", "ux", "uy", "uz", "T"]          # bit order of LBM_FIELD_*
 LAT = {"D2Q9": LBM_D2Q9, "D3Q7": LBM_D3Q7, "D3Q19": LBM_D3Q19}
@@ -48,6 +52,11 @@ class lbm_params(C.Structure):
         ("bc", C.c_int32 * 3),
         ("phi_wall", (C.c_double * 2) * 3), ("T_wall", (C.c_double * 2) * 3),
         ("eps_n", C.c_double),
+        ("collision", C.c_int32),
+        ("trt_lambda", C.c_double * 3),
+        ("mrt_rates", (C.c_double * 4) * 3),
+        ("grad_scheme", C.c_int32),
+        ("check_every", C.c_int32),
     ]
 
 
@@ -76,10 +85,10 @@ def load_library(path: str = LIB_PATH):
         "lbm_set_state": (I32, [P, P, SZ]),
         "lbm_get_step": (I32, [P, C.POINTER(I64)]),
         "lbm_sync": (I32, [P]),
-        "lbm_tape_size": (I32, [P, I64, C.POINTER(SZ)]),
-        "lbm_forward_taped": (I32, [P, I64, P, SZ]),
+        "lbm_tape_size": (I32, [P, I64, I32, C.POINTER(SZ)]),
+        "lbm_forward_taped": (I32, [P, I64, I32, P, SZ]),
         "lbm_adjoint_workspace_size": (I32, [P, C.POINTER(SZ)]),
-        "lbm_backward": (I32, [P, P, I32, P, SZ, P, P, P, I32, I32, I32]),
+        "lbm_backward": (I32, [P, P, P, P, P, I32, P, SZ, P, P, P, I32, I32, I32]),
         "lbm_destroy": (None, [P]),
         "lbm_last_error": (C.c_char_p, []),
         "lbm_version": (C.c_char_p, []),
@@ -109,7 +118,17 @@ def make_params(prm: dict, storage: str) -> lbm_params:
     flags |= LBM_PHASE_CHANGE if (prm["phase_change"] and prm["heat"]) else 0
     flags |= LBM_VISC_LINEAR if prm["visc_linear"] else 0
     flags |= LBM_GEQ_CAC if prm["geq_cac"] else 0
+    flags |= LBM_DIV_LOCAL if prm.get("div_local", False) else 0
     p.flags = flags
+    p.collision = COLL[prm.get("collision", "bgk")]
+    lam = prm.get("trt_lambda", (0.25, 0.25, 0.25))
+    rates = prm.get("mrt_rates", ((1.0,) * 4,) * 3)
+    for k in range(3):
+        p.trt_lambda[k] = float(lam[k])
+        for r in range(4):
+            p.mrt_rates[k][r] = float(rates[k][r])
+    p.grad_scheme = GRAD[prm.get("grad_scheme", "central")]
+    p.check_every = int(prm.get("check_every", 0))
     for k in ("nu_l", "nu_g", "mobility", "alpha_l", "alpha_g", "W", "sigma", "rho_l", "rho_g",
               "L_over_cp", "T_sat", "theta_I", "A_coef", "eps_n"):
         setattr(p, k, float(prm[k]))
@@ -255,19 +274,22 @@ class Sim:
         off = (-t.data_ptr()) % 256
         return t, t.data_ptr() + off
 
-    def forward_taped(self, nsteps: int):
-        """Advance nsteps recording the sqrt(T) tape for backward()."""
+    def forward_taped(self, nsteps: int, policy: int = LBM_TAPE_SQRT):
+        """Advance nsteps from a fresh init recording the tape for backward()."""
         n = C.c_size_t()
-        _check(self.lib.lbm_tape_size(self.ctx, int(nsteps), C.byref(n)))
+        _check(self.lib.lbm_tape_size(self.ctx, int(nsteps), int(policy), C.byref(n)))
         self._tape, ptr = self._aligned(n.value, self.device)
-        _check(self.lib.lbm_forward_taped(self.ctx, int(nsteps), C.c_void_p(ptr), n))
+        _check(self.lib.lbm_forward_taped(self.ctx, int(nsteps), int(policy), C.c_void_p(ptr), n))
         return self
 
-    def backward(self, gphi, tw_face=(1, 0)) -> dict:
-        """Gradients of a loss with dL/dphi^N = gphi (array [ny][nx]) with
-        respect to phi0, T0 and the wall-temperature face tw_face."""
+    def backward(self, gphi=None, tw_face=(1, 0), gT=None) -> dict:
+        """Gradients of a loss with dL/dphi^N = gphi and dL/dT^N = gT (arrays
+        [ny][nx], each optional) with respect to phi0, T0 and the
+        wall-temperature face tw_face."""
         torch = self.torch
-        g = self._dev(gphi, torch.float64).reshape(self.shape[1:]).contiguous()
+        shp = self.shape[1:]
+        g = None if gphi is None else self._dev(gphi, torch.float64).reshape(shp).contiguous()
+        gt = None if gT is None else self._dev(gT, torch.float64).reshape(shp).contiguous()
         n = C.c_size_t()
         _check(self.lib.lbm_adjoint_workspace_size(self.ctx, C.byref(n)))
         ws, ptr = self._aligned(n.value, self.device)
@@ -276,9 +298,10 @@ class Sim:
         dT0 = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
         face_len = nx if tw_face[0] == 1 else ny
         dTw = torch.empty(face_len, dtype=torch.float64, device=self.device)
-        _check(self.lib.lbm_backward(self.ctx, self._ptr(g), LBM_DT_F64, C.c_void_p(ptr), n,
-                                     self._ptr(dphi), self._ptr(dT0), self._ptr(dTw),
-                                     int(tw_face[0]), int(tw_face[1]), LBM_DT_F64))
+        none = C.c_void_p(None)
+        _check(self.lib.lbm_backward(self.ctx, self._ptr(g), self._ptr(gt), none, none, LBM_DT_F64,
+                                     C.c_void_p(ptr), n, self._ptr(dphi), self._ptr(dT0),
+                                     self._ptr(dTw), int(tw_face[0]), int(tw_face[1]), LBM_DT_F64))
         self._keep_ws = ws
         return dict(phi0=dphi, T0=dT0, Tw=dTw)
 

@@ -38,9 +38,35 @@ def test_version_and_error_string(lib):
     assert lib.lbm_last_error() is not None
 
 
+def _c_layout():
+    """sizeof(lbm_params) and the offset of every field, from the C header
+    compiled by the host C compiler."""
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    names = [f[0] for f in lbm.lbm_params._fields_]
+    body = "\n".join(f'  printf("{n} %zu\\n", offsetof(lbm_params, {n}));' for n in names)
+    src = ("#include <stdio.h>\n#include <stddef.h>\n#include \"lbm.h\"\nint main(void){\n"
+           '  printf("sizeof %zu\\n", sizeof(lbm_params));\n' + body + "\n  return 0;\n}\n")
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(src)
+        subprocess.run([cc, "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    return {k: int(v) for k, v in (ln.split() for ln in out.splitlines())}
+
+
 def test_struct_layout_matches_header():
-    # the Python mirror of lbm_params must have the C size (same field order)
-    assert C.sizeof(lbm.lbm_params) == 4 * 9 + 4 + 8 * 13 + 8 * 6 + 4 * 3 + 4 + 8 * 12 + 8
+    """The ctypes mirror of lbm_params has the C size and every field at the
+    C offset (same order, types and padding)."""
+    lay = _c_layout()
+    assert C.sizeof(lbm.lbm_params) == lay["sizeof"]
+    for name, _ in lbm.lbm_params._fields_:
+        assert getattr(lbm.lbm_params, name).offset == lay[name], name
 
 
 def _status(prm, storage="f32"):
@@ -102,10 +128,12 @@ def test_walled_axis_needs_two_nodes(lib):
 
 
 def test_stream_probe_library_loads_and_checks_arguments():
-    """The measurement probe bench.py times beside the step (its own
-    library, outside the C ABI) is built, exports its launcher, and rejects
-    null buffers and grids below 3 x 3 before any device call."""
-    path = os.path.join(os.path.dirname(lbm.LIB_PATH), "libstream_probe.so")
+    """The measurement probes bench.py times beside the step (their own
+    library, outside the C ABI) are built, export their launchers, and
+    reject null buffers, grids below 3 x 3 and misaligned copies before any
+    device call."""
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "benchprobe",
+                        "libstream_probe.so")
     if not os.path.exists(path):
         pytest.fail("libstream_probe.so is not built (run __graft_entry__.build())")
     p = C.CDLL(path)
@@ -114,3 +142,9 @@ def test_stream_probe_library_loads_and_checks_arguments():
     f.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
     assert f(None, None, 64, 64, None) != 0
     assert f(C.c_void_p(16), C.c_void_p(32), 2, 64, None) != 0
+    g = p.stream_probe_copy16
+    g.restype = C.c_int
+    g.argtypes = [C.c_void_p, C.c_void_p, C.c_longlong, C.c_int, C.c_void_p]
+    assert g(None, None, 1024, 0, None) != 0
+    assert g(C.c_void_p(16), C.c_void_p(32), 1000, 0, None) != 0   # not a multiple of 16
+    assert g(C.c_void_p(8), C.c_void_p(32), 1024, 1, None) != 0    # misaligned source

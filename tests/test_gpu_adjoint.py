@@ -132,8 +132,9 @@ def test_adjoint_sqrtT_segments_match_oracle():
     assert e_phi < 1e-9 and e_tw < 1e-9
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("n,bar", [(300, 1e-4), (1000, 1e-4)])
-def test_adjoint_vs_central_fd_config4_size(n, bar):
+def test_adjoint_vs_central_fd_config4_size(n, bar, storage):
     """512 x 512 film (lambda = 512 gravity, h = 32 + 2 cos + noise, T_w ~
     N(1, 0.05^2)), FP64: directional derivatives of V along 16 random unit
     directions of T_w and of phi0 vs central differences (step 1e-4),
@@ -152,8 +153,8 @@ def test_adjoint_vs_central_fd_config4_size(n, bar):
     phi0, T0, _ = I.film2d_fields(prm, seed=2, h0=32.0, amp=2.0)
     Tw = I.wall_T_row(nx, seed=3)
     t0 = time.time()
-    V, g = gpu_value_and_grad(prm, phi0, T0, Tw, n)
-    say(f"[adjoint] 512^2 x {n} forward+backward {time.time() - t0:.1f}s, V = {V:.8f}")
+    V, g = gpu_value_and_grad(prm, phi0, T0, Tw, n, storage=storage)
+    say(f"[adjoint] 512^2 x {n} {storage} forward+backward {time.time() - t0:.1f}s, V = {V:.8f}")
     dirs_tw = I.random_directions(nx, 16, seed=4)
     dirs_phi = I.random_directions(nx * ny, 16, seed=5)
     fds = {"Tw": [], "phi0": []}
@@ -180,27 +181,194 @@ def test_adjoint_vs_central_fd_config4_size(n, bar):
     # changes carries the difference quotient's absolute error only
     for kind in ("Tw", "phi0"):
         e = rel_l2(ads[kind], fds[kind])
-        say(f"[adjoint] n={n} {kind}: relative L2 over 16 directions {e:.2e}")
+        say(f"[adjoint] n={n} {storage} {kind}: relative L2 over 16 directions {e:.2e}")
         assert e <= bar, (kind, e)
+
+
+def _oracle_grads(prm, phi0, T0, Tw, n, loss, dtype=F64):
+    """Oracle reverse pass (torch.autograd through the oracle evaluated in
+    `dtype`) of loss(phi^N, T^N): gradients w.r.t. phi0, T0 and T_w."""
+    phi = torch.tensor(phi0, dtype=dtype, requires_grad=True)
+    T0t = torch.tensor(T0, dtype=dtype, requires_grad=True)
+    tw = torch.tensor(Tw, dtype=dtype, requires_grad=True)
+    M = Model(prm, T_wall_faces={(1, 0): tw.reshape(1, 1, -1)}, dtype=dtype)
+    f = M.fields(M.run(M.init(phi, T0t), n))
+    loss(f["phi"], f["T"]).backward()
+    return {"phi0": phi.grad.double().numpy()[0], "T0": T0t.grad.double().numpy()[0],
+            "Tw": tw.grad.double().numpy()}
+
+
+def _lbmrun_grads(prm, phi0, T0, Tw, n, storage, loss):
+    from paper_2003_06342_amd.autograd import LBMRun
+    phi_g = torch.tensor(phi0, dtype=F64, device="cuda", requires_grad=True)
+    tw_g = torch.tensor(Tw, dtype=F64, device="cuda", requires_grad=True)
+    phiN, TN = LBMRun.apply(phi_g, tw_g, prm, T0, n, storage)
+    loss(phiN, TN).backward()
+    return {"phi0": phi_g.grad.cpu().numpy()[0], "Tw": tw_g.grad.cpu().numpy()}
+
+
+def _sq_phi_plus_T(phi, T):
+    return (phi ** 2).mean() + 0.3 * T.mean()
 
 
 def test_autograd_function_matches_oracle():
     """The torch.autograd.Function bridge (LBMRun) on CUDA tensors: the
-    gradients reaching phi0 and T_w through loss.backward() equal the FP64
-    oracle's reverse pass."""
+    gradients of a loss of phi^N and T^N reaching phi0 and T_w through
+    loss.backward() equal the FP64 oracle's reverse pass."""
     need_gpu()
-    from paper_2003_06342_amd.autograd import LBMRun
     prm, phi0, T0, Tw = film(24, 20, 6.0, 1.5, g=2e-4)
     n = 12
-    phi_o = torch.tensor(phi0, dtype=F64, requires_grad=True)
-    tw_o = torch.tensor(Tw, dtype=F64, requires_grad=True)
-    M = Model(prm, T_wall_faces={(1, 0): tw_o.reshape(1, 1, -1)})
-    (M.fields(M.run(M.init(phi_o, T0), n))["phi"] ** 2).mean().backward()
-    phi_g = torch.tensor(phi0, dtype=F64, device="cuda", requires_grad=True)
-    tw_g = torch.tensor(Tw, dtype=F64, device="cuda", requires_grad=True)
-    phiN = LBMRun.apply(phi_g, tw_g, prm, T0, n, "f64")
-    (phiN ** 2).mean().backward()
-    e_phi = rel_l2(phi_g.grad.cpu().numpy(), phi_o.grad.numpy())
-    e_tw = rel_l2(tw_g.grad.cpu().numpy(), tw_o.grad.numpy())
+    ref = _oracle_grads(prm, phi0, T0, Tw, n, _sq_phi_plus_T)
+    g = _lbmrun_grads(prm, phi0, T0, Tw, n, "f64", _sq_phi_plus_T)
+    e_phi = rel_l2(g["phi0"], ref["phi0"])
+    e_tw = rel_l2(g["Tw"], ref["Tw"])
     say(f"[adjoint] autograd.Function: dphi0 {e_phi:.2e} dTw {e_tw:.2e}")
     assert e_phi < 1e-9 and e_tw < 1e-9
+
+
+@pytest.mark.parametrize("which", ["T", "phi+T"])
+def test_adjoint_temperature_seed_matches_oracle_f64(which):
+    """A loss of the final temperature (dL/dT^N through lbm_backward's g_T
+    seed: the pulled s, the latent-heat term's phi, phi_prev and the
+    transposed div(u phi)), alone and with a phi^N term, against the FP64
+    oracle's reverse pass."""
+    need_gpu()
+    from paper_2003_06342_amd import lbm
+    prm, phi0, T0, Tw = film(24, 20, 6.0, 1.5, g=2e-4)
+    n = 12
+    rng = np.random.default_rng(7)
+    wT = rng.standard_normal((prm["ny"], prm["nx"]))
+    wphi = rng.standard_normal((prm["ny"], prm["nx"])) if which == "phi+T" else None
+
+    def loss(phi, T):
+        out = (torch.as_tensor(wT, dtype=T.dtype) * T[0]).sum()
+        if wphi is not None:
+            out = out + (torch.as_tensor(wphi, dtype=phi.dtype) * phi[0]).sum()
+        return out
+    ref = _oracle_grads(prm, phi0, T0, Tw, n, loss)
+    sim = lbm.Sim(prm, "f64")
+    sim.set_wall_T(1, 0, Tw)
+    sim.init(phi0, T0)
+    sim.forward_taped(n)
+    g = sim.backward(wphi, gT=wT)
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    sim.sync()
+    sim.close()
+    errs = {k: rel_l2(g[k], ref[k]) for k in ("phi0", "T0", "Tw")}
+    say(f"[adjoint] T seed ({which}): {errs}")
+    for k, e in errs.items():
+        assert e < 1e-9, (k, errs)
+
+
+# ---- FP32 storage: the path LBMRun defaults to and bench.py times ----------
+
+def _f32_bar(prm, phi0, T0, Tw, n, loss):
+    """FP32 bar per gradient: the relative L2 between the oracle's reverse
+    pass evaluated in float32 and in float64 (the rounding floor of any FP32
+    evaluation of this adjoint), times 3, and at least 1e-5."""
+    r64 = _oracle_grads(prm, phi0, T0, Tw, n, loss)
+    r32 = _oracle_grads(prm, phi0, T0, Tw, n, loss, dtype=torch.float32)
+    floor = {k: rel_l2(r32[k], r64[k]) for k in r64}
+    return r64, floor, {k: max(1e-5, 3.0 * v) for k, v in floor.items()}
+
+
+@pytest.mark.parametrize("n", [12, 31])
+def test_adjoint_f32_matches_oracle(n):
+    """FP32 storage and arithmetic: gradients of V = mean phi^N after 12
+    steps, and after 31 steps (several sqrt(T) tape segments), against the
+    FP64 oracle's reverse pass, within the FP32 floor bar."""
+    need_gpu()
+    prm, phi0, T0, Tw = film(24, 20, 6.0, 1.5, g=2e-4) if n == 12 else film(32, 24, 7.0, 1.5, g=2e-4)
+    ref, floor, bars = _f32_bar(prm, phi0, T0, Tw, n, lambda p, T: p.mean())
+    _, g = gpu_value_and_grad(prm, phi0, T0, Tw, n, storage="f32")
+    errs = {k: rel_l2(g[k], ref[k]) for k in ("phi0", "T0", "Tw")}
+    say(f"[adjoint] f32 n={n}: gpu {errs} | fp32 floor {floor}")
+    for k in errs:
+        assert errs[k] <= bars[k], (k, errs, floor)
+
+
+def test_autograd_function_f32_matches_oracle():
+    """LBMRun with its default FP32 storage against the FP64 oracle's
+    reverse pass (loss of phi^N and T^N), within the FP32 floor bar."""
+    need_gpu()
+    prm, phi0, T0, Tw = film(24, 20, 6.0, 1.5, g=2e-4)
+    n = 12
+    ref, floor, bars = _f32_bar(prm, phi0, T0, Tw, n, _sq_phi_plus_T)
+    g = _lbmrun_grads(prm, phi0, T0, Tw, n, "f32", _sq_phi_plus_T)
+    errs = {k: rel_l2(g[k], ref[k]) for k in ("phi0", "Tw")}
+    say(f"[adjoint] autograd.Function f32: gpu {errs} | fp32 floor {floor}")
+    for k in errs:
+        assert errs[k] <= bars[k], (k, errs, floor)
+
+
+# ---- state guards of the tape ------------------------------------------------
+
+def _status_of(fn):
+    from paper_2003_06342_amd import lbm
+    try:
+        fn()
+    except lbm.LBMError as e:
+        return e.status
+    return lbm.LBM_OK
+
+
+def test_stale_tape_and_state_guards():
+    """lbm_backward refuses a tape that no longer describes the context
+    (re-initialised, state set, wall temperature changed, stepped), and
+    lbm_forward_taped refuses a state it cannot differentiate (after steps,
+    after set_state, after an init with u0)."""
+    need_gpu()
+    from paper_2003_06342_amd import lbm
+    prm, phi0, T0, Tw = film(24, 20, 6.0, 1.5, g=2e-4)
+    g = np.full((prm["ny"], prm["nx"]), 1.0 / (prm["nx"] * prm["ny"]))
+    sim = lbm.Sim(prm, "f64")
+    sim.set_wall_T(1, 0, Tw)
+
+    def taped():
+        sim.init(phi0, T0)
+        sim.forward_taped(6)
+    taped()
+    blob = sim.get_state()
+    sim.init(phi0, T0)
+    sim.step(6)          # same step count as the tape: only the re-init tells
+    assert _status_of(lambda: sim.backward(g)) == lbm.LBM_E_STATE
+    taped()
+    sim.set_state(blob)
+    assert _status_of(lambda: sim.backward(g)) == lbm.LBM_E_STATE
+    taped()
+    sim.set_wall_T(1, 0, Tw + 0.1)
+    assert _status_of(lambda: sim.backward(g)) == lbm.LBM_E_STATE
+    sim.set_wall_T(1, 0, Tw)
+    taped()
+    sim.step(1)
+    assert _status_of(lambda: sim.backward(g)) == lbm.LBM_E_STATE
+    # forward_taped needs step 0 of an init without u0
+    sim.init(phi0, T0)
+    sim.step(2)
+    assert _status_of(lambda: sim.forward_taped(4)) == lbm.LBM_E_STATE
+    sim.set_state(blob)
+    assert _status_of(lambda: sim.forward_taped(4)) == lbm.LBM_E_STATE
+    u0 = [np.zeros_like(phi0)] * 3
+    sim.init(phi0, T0, u0=u0)
+    assert _status_of(lambda: sim.forward_taped(4)) == lbm.LBM_E_STATE
+    # a valid sequence still works, and g_u / g_p seeds are refused explicitly
+    taped()
+    out = sim.backward(g)
+    assert np.isfinite(out["phi0"].cpu().numpy()).all()
+    import ctypes as C
+    n = C.c_size_t()
+    lib = lbm.load_library()
+    assert lib.lbm_adjoint_workspace_size(sim.ctx, C.byref(n)) == lbm.LBM_OK
+    ws = torch.empty(n.value + 256, dtype=torch.uint8, device="cuda")
+    wp = C.c_void_p((ws.data_ptr() + 255) // 256 * 256)
+    gd = torch.tensor(g, dtype=F64, device="cuda")
+    gp = C.c_void_p(gd.data_ptr())
+    none = C.c_void_p(None)
+    st = lib.lbm_backward(sim.ctx, gp, none, gp, none, lbm.LBM_DT_F64, wp, n, none, none, none,
+                          1, 0, lbm.LBM_DT_F64)
+    assert st == lbm.LBM_E_UNSUPPORTED
+    st = lib.lbm_backward(sim.ctx, none, none, none, none, lbm.LBM_DT_F64, wp, n, none, none, none,
+                          1, 0, lbm.LBM_DT_F64)
+    assert st == lbm.LBM_E_INVAL
+    sim.sync()
+    sim.close()

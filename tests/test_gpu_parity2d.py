@@ -255,3 +255,50 @@ def test_static_drop_128_500_steps_f64():
     errs, gpu, ref = _check("drop128_f64", prm, phi0, None, 500, "f64", 1e-10)
     m0 = float(phi0.sum())
     assert abs(gpu["diag"]["mass"] - m0) / m0 < 1e-13
+
+
+def _box_case(nx, ny):
+    """A closed 2-D box: walls on x and y (both anti-bounce-back families
+    and bounce-back f), heated floor, the corner rule of reading R13."""
+    prm = I.film2d_params(nx, ny)
+    prm["bc"] = ["wall", "wall", "periodic"]
+    prm["phi_wall"] = [[1.0, 1.0], [1.0, 1.0], [0.0, 0.0]]
+    prm["T_wall"] = [[0.2, 0.1], [1.0, 0.0], [0.0, 0.0]]
+    prm["gravity"] = [0.0, -2e-5, 0.0]
+    phi0, T0, _ = I.film2d_fields(prm, seed=4, h0=10.0, amp=2.0)
+    return prm, phi0, T0
+
+
+def test_box_two_walled_axes_f64():
+    """Walls on both axes (130 x 66: ragged tiles in x and y): the corner
+    precedence of the pulls and the composed stencil ghosts at the corners,
+    against the oracle in FP64."""
+    prm, phi0, T0 = _box_case(130, 66)
+    _check("box_f64", prm, phi0, T0, 60, "f64", 1e-10)
+
+
+def test_box_two_walled_axes_f32():
+    prm, phi0, T0 = _box_case(70, 19)
+    _check_f32("box_f32", prm, phi0, T0, 60)
+
+
+def test_check_every_reports_unstable_and_leaves_healthy_runs_unchanged():
+    """check_every > 0: a run whose initial field holds a NaN returns
+    LBM_E_UNSTABLE at the first check, with the step count at that check; a
+    healthy run with checks equals the same run without them bit for bit."""
+    need_gpu()
+    from paper_2003_06342_amd import lbm
+    prm, phi0, T0 = film_case(70, 40, 8.0, 1.5)
+    ref = gpu_run(prm, phi0, T0, 12, "f32")
+    prm_c = dict(prm, check_every=5)
+    chk = gpu_run(prm_c, phi0, T0, 12, "f32")
+    for k in ("phi", "T", "ux", "p"):
+        assert np.array_equal(ref[k], chk[k]), k
+    bad = phi0.copy()
+    bad[0, 20, 30] = np.nan
+    sim = lbm.Sim(dict(prm, check_every=3), "f32").init(bad, T0)
+    with pytest.raises(lbm.LBMError) as e:
+        sim.step(10)
+    assert e.value.status == lbm.LBM_E_UNSTABLE
+    assert sim.steps_taken == 3
+    sim.close()

@@ -6,7 +6,13 @@ population (per-node references, the lagged phi plane and a T_ref plane).
 Measured (relative L2 after 100 steps in 2-D, 40 in 3-D): FP16 phi 7e-6 /
 1.5e-5, T 7e-5 / 7e-5, |u| 5e-4 / 4e-4, p 1.0e-3 / 4e-4 (2-D / 3-D).  The
 per-node references took T from 5e-3 and phi from 5e-4.  BF16 is about 8x
-worse (3 fewer mantissa bits).  The bars are these levels with margin."""
+worse (3 fewer mantissa bits).
+
+Bars: FP16 phi, T and |u| within the 1e-3 compressed-storage target (phi
+1e-4, T and |u| 1e-3); the pressure, about its mean, is reported beside them
+(the error headline is the worst of phi, T and |u|) with a sanity bar of
+3e-3.  BF16 misses the 1e-3 target for |u| and p; its bars record the
+measured levels with margin."""
 import numpy as np
 import pytest
 
@@ -43,7 +49,7 @@ def test_deviation_storage(storage, case, steps):
     e16, e32 = compare(g16, ref), compare(g32, ref)
     say(f"[storage16] {case} {storage}: {e16} | f32 {e32}")
     assert all(np.isfinite(v) for v in e16.values())
-    bars = ({"phi": 1e-4, "T": 1e-3, "umag": 2e-3, "p": 3e-3} if storage == "f16dev" else
+    bars = ({"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 3e-3} if storage == "f16dev" else
             {"phi": 1e-3, "T": 5e-3, "umag": 2e-2, "p": 5e-2})
     for k, bar in bars.items():
         assert e16[k] <= bar, (k, e16)
@@ -74,7 +80,8 @@ def test_compressed_storage_64cubed_instance_of_512cubed_run():
         assert errs["f16dev"][k] <= 1e-3, ("f16dev", k, errs["f16dev"])
         assert errs["bf16dev"][k] <= 2e-2, ("bf16dev", k, errs["bf16dev"])
     assert errs["f16dev"]["p"] <= 3e-3
-    assert errs["f32"]["phi"] <= 1e-5 and errs["f32"]["T"] <= 1e-5, errs["f32"]
+    for k in ("phi", "T", "umag", "p"):
+        assert errs["f32"][k] <= 1e-5, ("f32", k, errs["f32"])
 
 
 def test_deviation_storage_full_size_bench_grid():
@@ -88,7 +95,7 @@ def test_deviation_storage_full_size_bench_grid():
     n = 20
     say(f"[storage16] full size 1024x2048: oracle {n} steps")
     ref = oracle_run(prm, phi0, T0, n)
-    for storage, bars in (("f16dev", {"phi": 1e-4, "T": 1e-3, "umag": 2e-3, "p": 3e-3}),
+    for storage, bars in (("f16dev", {"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 3e-3}),
                           ("bf16dev", {"phi": 1e-3, "T": 5e-3, "umag": 2e-2, "p": 5e-2})):
         e = compare(gpu_run(prm, phi0, T0, n, storage), ref)
         say(f"[storage16] full size {storage}: {e}")
