@@ -39,6 +39,8 @@ same ones):
   R7  d_t phi = phi^n - phi^{n-1} (0 at the first step).
   R8  div(u phi) = sum_a of the a-th component of the Eq. Grad stencil applied
       to u_a phi.
+  R8b with div_local: u.grad(phi) + phi div(u), div(u) from Eq.
+      ConservMasse_ChgtPhase with the previous step's production.
   R9  n = grad(phi) / sqrt(|grad(phi)|^2 + eps^2), eps = 1e-3: far below
       interface gradients (~1/W), far above round-off gradients in the bulk
       phases, where a smaller eps turns round-off into O(phi(1-phi)) forcing.
@@ -50,6 +52,21 @@ same ones):
       axis (z over y over x) gives the anti-bounce-back value.
   R17 the u of the current step enters Gamma_i of all three families.
   R18 the pressure moment uses the current step's q.
+  R26 TRT and MRT (named in Sec. 3 after Eq. LBE as the way to lower
+      mobility and higher Peclet numbers; not written out in the paper) act
+      on the same barred variables as BGK: the non-equilibrium plus half the
+      source, a_i = pop_i - eq_i + S_i/2, relaxes and S_i is added, so equal
+      rates give BGK exactly.  TRT (Ginzburg) relaxes the parts of a
+      symmetric and antisymmetric under c -> -c with omega+ and omega-; the
+      transport coefficient keeps its BGK rate (omega+ for the viscosity of
+      f, omega- for the mobility of g and the diffusivity of s) and the other
+      rate follows from Lambda = (1/omega+ - 1/2)(1/omega- - 1/2).  MRT
+      (d'Humieres) relaxes a in an orthogonal moment basis: D2Q9 rho, e, eps,
+      jx, qx, jy, qy, pxx, pxy (Lallemand and Luo); D3Q7 1, cx, cy, cz,
+      7c^2 - 6, 2cx^2 - cy^2 - cz^2, cy^2 - cz^2.  Transport moments at the
+      BGK rate (pxx, pxy for f; j for g and s), the others at the free rates
+      (s_e for rho and e, s_eps, s_q for q (and j of f), s_p for the
+      second-order moments of g and s).
 Parity unpinned beyond self-consistency and invariants: R6-R10, R13 as
 modelling choices, and chaotic trajectories after pinch-off.
 """
@@ -197,6 +214,16 @@ class Model:
         self.grav = [float(v) for v in prm["gravity"]]
         self.body = [float(v) for v in prm.get("body_force", (0.0, 0.0, 0.0))]
         self.eps = float(prm.get("eps_n", 1e-3))
+        self.div_local = bool(prm.get("div_local", False))
+        if self.div_local and not (self.ns and self.heat):
+            raise ValueError("div_local needs the NS and heat families")
+        self.collision = prm.get("collision", "bgk")
+        if self.collision not in ("bgk", "trt", "mrt"):
+            raise ValueError(self.collision)
+        self.trt_lambda = [float(v) if v > 0 else 0.25
+                           for v in prm.get("trt_lambda", (0.25, 0.25, 0.25))]
+        self.mrt_rates = [[float(r) for r in fam]
+                          for fam in prm.get("mrt_rates", ((1.0,) * 4,) * 3)]
         # Eq. Def_K-H
         self.K = 1.5 * self.W * self.sigma
         self.H = 12.0 * self.sigma / self.W
@@ -300,6 +327,16 @@ class Model:
             D = D + self.grad(prod)[a]
         return D
 
+    def divergence_term(self, u, phi_padded, grad_phi, phi, q_prev):
+        """The div(u phi) of the latent-heat source: R8 (central stencil), or
+        with ``div_local`` (R8b) u.grad(phi) + phi div(u), where div(u) =
+        mdot (1/rho_g - 1/rho_l) (Eq. ConservMasse_ChgtPhase) with the
+        production of the previous step, mdot = rho_g q_prev (as R6)."""
+        if not self.div_local:
+            return self.divergence(u, phi_padded)
+        udg = sum(u[a] * grad_phi[a] for a in range(3))
+        return udg + phi * self.rho_g * q_prev * (1.0 / self.rho_g - 1.0 / self.rho_l)
+
     def production(self, phi, T, alpha):
         """q = m'''/rho_g of Eq. ProductionRate with theta = (Cp/L)(T - T_sat)."""
         if not self.phase_change:
@@ -337,7 +374,7 @@ class Model:
         dtphi = phi - st.phi_prev
         alpha = self.diffusivity(phi)
         if self.heat:
-            D = self.divergence(u, P)
+            D = self.divergence_term(u, P, gphi, phi, st.q_prev)
             # S5: Eq. Moment_Temp
             T = st.s.sum(0) - 0.5 * self.Lcp * (dtphi + D)
         else:
@@ -419,22 +456,75 @@ class Model:
         """Eq. LBE with Eq. VariableChange_feq: bar-eq = eq - S/2."""
         return pop_i - omega * (pop_i - (eq_i - 0.5 * S_i)) + S_i
 
+    @staticmethod
+    def trt(L: Lattice, pop, eq, S, om_plus, om_minus):
+        """Two-relaxation-time collision (R26): a = pop - eq + S/2 split into
+        its parts symmetric and antisymmetric under c_i -> -c_i."""
+        a = [pop[i] - eq[i] + 0.5 * S[i] for i in range(L.Q)]
+        out = []
+        for i in range(L.Q):
+            j = L.opp[i]
+            sym = 0.5 * (a[i] + a[j])
+            anti = 0.5 * (a[i] - a[j])
+            out.append(pop[i] - om_plus * sym - om_minus * anti + S[i])
+        return torch.stack(out)
+
+    @staticmethod
+    def mrt(L: Lattice, pop, eq, S, rates):
+        """Multiple-relaxation-time collision (R26): the moments m_k =
+        sum_i M_ki a_i of a = pop - eq + S/2 relax with rates[k]; M has
+        orthogonal rows, so the inverse map is M^T divided by the squared row
+        norms."""
+        Mx = moment_basis(L)
+        Q = L.Q
+        norms = [sum(Mx[k][i] ** 2 for i in range(Q)) for k in range(Q)]
+        a = [pop[i] - eq[i] + 0.5 * S[i] for i in range(Q)]
+        m = [sum(Mx[k][i] * a[i] for i in range(Q) if Mx[k][i] != 0) for k in range(Q)]
+        dm = [rates[k] * m[k] / norms[k] for k in range(Q)]
+        out = []
+        for i in range(Q):
+            back = sum(Mx[k][i] * dm[k] for k in range(Q) if Mx[k][i] != 0)
+            out.append(pop[i] - back + S[i])
+        return torch.stack(out)
+
+    def relax(self, family: int, L: Lattice, pop, eq, S, tau):
+        """Collision of one family (0 f, 1 g, 2 s) whose transport
+        coefficient gives tau (tau = diffusivity / c_s^2, a number or a
+        per-node tensor): BGK (Eq. LBE), TRT or MRT (R26)."""
+        om = 1.0 / (tau + 0.5)
+        if self.collision == "bgk":
+            return torch.stack([self.bgk(pop[i], eq[i], S[i], om) for i in range(L.Q)])
+        if self.collision == "trt":
+            lam = self.trt_lambda[family]
+            other = 1.0 / (lam / tau + 0.5)      # (1/w - 1/2) = Lambda / tau
+            if family == 0:
+                return self.trt(L, pop, eq, S, om, other)
+            return self.trt(L, pop, eq, S, other, om)
+        s_e, s_eps, s_q, s_p = self.mrt_rates[family]
+        if L.name == "D2Q9":
+            if family == 0:   # rho, e, eps, jx, qx, jy, qy, pxx, pxy
+                rates = [s_e, s_e, s_eps, s_q, s_q, s_q, s_q, om, om]
+            else:
+                rates = [s_e, s_e, s_eps, om, s_q, om, s_q, s_p, s_p]
+        elif L.name in ("D3Q7", "D2Q5") and family != 0:
+            if L.name == "D3Q7":   # 1, cx, cy, cz, 7c^2 - 6, 2cx^2 - cy^2 - cz^2, cy^2 - cz^2
+                rates = [s_e, om, om, om, s_e, s_p, s_p]
+            else:                  # 1, cx, cy, 5c^2 - 4, cx^2 - cy^2
+                rates = [s_e, om, om, s_e, s_p]
+        else:
+            raise ValueError(f"MRT is not defined here for {L.name} (family {family})")
+        return self.mrt(L, pop, eq, S, rates)
+
     def collide(self, st: State, m: Macros):
         out_f = out_s = None
         if self.ns:
             feq, S = self.f_terms(m)
-            om = 1.0 / (m.nu / self.Lf.cs2 + 0.5)          # tau_f = nu/c_s^2
-            out_f = torch.stack([self.bgk(st.f[i], feq[i], S[i], om)
-                                 for i in range(self.Lf.Q)])
+            out_f = self.relax(0, self.Lf, st.f, feq, S, m.nu / self.Lf.cs2)   # nu = tau_f c_s^2
         geq, S = self.g_terms(m)
-        om_g = 1.0 / (self.M / self.Lg.cs2 + 0.5)            # M = tau_g c_s^2
-        out_g = torch.stack([self.bgk(st.g[i], geq[i], S[i], om_g)
-                             for i in range(self.Lg.Q)])
+        out_g = self.relax(1, self.Lg, st.g, geq, S, self.M / self.Lg.cs2)     # M = tau_g c_s^2
         if self.heat:
             seq, S = self.s_terms(m)
-            om_s = 1.0 / (m.alpha / self.Ls.cs2 + 0.5)      # alpha = tau_s c_s^2
-            out_s = torch.stack([self.bgk(st.s[i], seq[i], S[i], om_s)
-                                 for i in range(self.Ls.Q)])
+            out_s = self.relax(2, self.Ls, st.s, seq, S, m.alpha / self.Ls.cs2)  # alpha = tau_s c_s^2
         return out_f, out_g, out_s
 
     # -- streaming with walls (S11) ---------------------------------------------
@@ -505,8 +595,10 @@ class Model:
         mu, rho, F = self.forces(phi, gphi, lphi)
         grho = [(self.rho_g - self.rho_l) * gphi[a] for a in range(3)]
         alpha = self.diffusivity(phi)
-        D = self.divergence(u, P) if self.heat else torch.zeros(self.shape, dtype=self.dt)
         q = self.production(phi, T, alpha) if self.heat else torch.zeros(self.shape, dtype=self.dt)
+        # the first step's div term sees q_prev = q(phi0, T0)
+        D = (self.divergence_term(u, P, gphi, phi, q) if self.heat
+             else torch.zeros(self.shape, dtype=self.dt))
         zero = torch.zeros(self.shape, dtype=self.dt)
         m = Macros(phi, gphi, lphi, n, mu, rho, grho, F, u, zero, D, T, q, p, alpha,
                    self.viscosity(phi))
@@ -539,6 +631,44 @@ class Model:
         N = m.phi.numel()
         return dict(mass=float(Phi), enthalpy=float(E), vapour=float(Phi) / N,
                     umax=float(umag.max()))
+
+
+def moment_basis(L: Lattice):
+    """Orthogonal moment basis of the MRT collision (R26) as a Q x Q list:
+    row k holds polynomial k evaluated at the lattice velocities c_i.
+    D2Q9 (Lallemand and Luo): 1, e = -4 + 3c^2, eps = 4 - 21c^2/2 + 9c^4/2,
+    cx, qx = (3c^2 - 5)cx, cy, qy = (3c^2 - 5)cy, cx^2 - cy^2, cx cy.
+    D3Q7: 1, cx, cy, cz, 7c^2 - 6, 2cx^2 - cy^2 - cz^2, cy^2 - cz^2.
+    D2Q5: 1, cx, cy, 5c^2 - 4, cx^2 - cy^2."""
+    def c2(c):
+        return c[0] ** 2 + c[1] ** 2 + c[2] ** 2
+    if L.name == "D2Q9":
+        polys = [lambda c: 1.0,
+                 lambda c: -4.0 + 3.0 * c2(c),
+                 lambda c: 4.0 - 10.5 * c2(c) + 4.5 * c2(c) ** 2,
+                 lambda c: float(c[0]),
+                 lambda c: (3.0 * c2(c) - 5.0) * c[0],
+                 lambda c: float(c[1]),
+                 lambda c: (3.0 * c2(c) - 5.0) * c[1],
+                 lambda c: float(c[0] ** 2 - c[1] ** 2),
+                 lambda c: float(c[0] * c[1])]
+    elif L.name == "D3Q7":
+        polys = [lambda c: 1.0,
+                 lambda c: float(c[0]),
+                 lambda c: float(c[1]),
+                 lambda c: float(c[2]),
+                 lambda c: 7.0 * c2(c) - 6.0,
+                 lambda c: float(2 * c[0] ** 2 - c[1] ** 2 - c[2] ** 2),
+                 lambda c: float(c[1] ** 2 - c[2] ** 2)]
+    elif L.name == "D2Q5":
+        polys = [lambda c: 1.0,
+                 lambda c: float(c[0]),
+                 lambda c: float(c[1]),
+                 lambda c: 5.0 * c2(c) - 4.0,
+                 lambda c: float(c[0] ** 2 - c[1] ** 2)]
+    else:
+        raise ValueError(f"no MRT basis for {L.name}")
+    return [[p(ci) for ci in L.c] for p in polys]
 
 
 def relative_l2(x, ref, about_mean: bool = False) -> float:
