@@ -67,6 +67,20 @@ same ones):
       BGK rate (pxx, pxy for f; j for g and s), the others at the free rates
       (s_e for rho and e, s_eps, s_q for q (and j of f), s_p for the
       second-order moments of g and s).
+  R27 biased directional derivatives (Sec. 3.4, after Eq. Laplacian: the
+      first- and second-order upwind differences phi(x + c) - phi(x) and
+      [-phi(x + 2c) + 4 phi(x + c) - 3 phi(x)] / 2, offered there as
+      alternatives to the central Eq. DerivDirec_Grad for low-density
+      regions, where the central form misses the velocity profile) replace
+      c_i . grad(phi) where the NS source projects it on its own direction
+      c_i: c_i . grad(rho) and the surface tension mu c_i . grad(phi) of Eq.
+      Forcing.  Every vector use of grad(phi) (u . grad(rho), u . F, the
+      velocity and pressure moments, the normal n) and the Laplacian keep
+      the central stencils, and so does c_i . n of Eq. SourceTerm_AllenCahn:
+      its zeroth moment must vanish for phi to stay conserved, which a
+      biased difference would break (sum_i w_i [phi(x + c_i) - phi(x)] is a
+      Laplacian).  Ghosts two nodes beyond a wall mirror the second node
+      (R13).
 Parity unpinned beyond self-consistency and invariants: R6-R10, R13 as
 modelling choices, and chaotic trajectories after pinch-off.
 """
@@ -164,6 +178,7 @@ class Macros:
     p: torch.Tensor
     alpha: torch.Tensor
     nu: torch.Tensor
+    phi_pad2: Optional[torch.Tensor] = None   # phi with two ghost layers (R27)
 
 
 def _tensor_axis(a: int) -> int:
@@ -217,6 +232,9 @@ class Model:
         self.div_local = bool(prm.get("div_local", False))
         if self.div_local and not (self.ns and self.heat):
             raise ValueError("div_local needs the NS and heat families")
+        self.grad_scheme = prm.get("grad_scheme", "central")
+        if self.grad_scheme not in ("central", "biased1", "biased2"):
+            raise ValueError(self.grad_scheme)
         self.collision = prm.get("collision", "bgk")
         if self.collision not in ("bgk", "trt", "mrt"):
             raise ValueError(self.collision)
@@ -276,6 +294,45 @@ class Model:
                 raise ValueError(kind)
             out = torch.cat([lo, out, hi], dim=d)
         return out
+
+    def ghost_pad_wide(self, v, kind: str, width: int):
+        """ghost_pad with `width` ghost layers: periodic axes wrap; the
+        ghost k nodes beyond a wall mirrors the k-th node from it (R13)."""
+        out = v
+        for a in range(3):
+            d = _tensor_axis(a)
+            n = out.shape[d]
+            idx = torch.arange(width)
+            if not self.wall[a]:
+                lo = out.index_select(d, (n - width + idx) % n)
+                hi = out.index_select(d, idx % n)
+            else:
+                lo = out.index_select(d, torch.flip(idx, [0]))       # ghost -k <- node k-1
+                hi = out.index_select(d, n - 1 - idx)                # ghost n-1+k <- node n-k
+                if kind == "phi":
+                    lo = 2.0 * self.phi_w[a][0] - lo
+                    hi = 2.0 * self.phi_w[a][1] - hi
+                else:
+                    raise ValueError(kind)
+            out = torch.cat([lo, out, hi], dim=d)
+        return out
+
+    def cproj(self, m, c):
+        """c . grad(phi) for a lattice velocity c under the directional-
+        derivative scheme (R27): the projection of the Eq. Grad vector
+        (central), or the first- / second-order biased difference along c."""
+        if all(x == 0 for x in c):
+            return torch.zeros(self.shape, dtype=self.dt)
+        if self.grad_scheme == "central":
+            return sum(c[a] * m.grad_phi[a] for a in range(3) if c[a] != 0)
+        nz, ny, nx = self.shape
+
+        def at(k):   # phi(x + k c) from the two-layer padded field
+            return m.phi_pad2[2 + k * c[2]:2 + k * c[2] + nz, 2 + k * c[1]:2 + k * c[1] + ny,
+                              2 + k * c[0]:2 + k * c[0] + nx]
+        if self.grad_scheme == "biased1":
+            return at(1) - at(0)
+        return 0.5 * (-at(2) + 4.0 * at(1) - 3.0 * at(0))
 
     def _shift(self, padded, e):
         """padded value at x + e for every interior node x."""
@@ -392,7 +449,10 @@ class Model:
         else:
             p = torch.zeros(self.shape, dtype=self.dt)
         return Macros(phi, gphi, lphi, n, mu, rho, grho, F, u, dtphi, D, T, q, p,
-                      alpha, self.viscosity(phi))
+                      alpha, self.viscosity(phi), self._pad2(phi))
+
+    def _pad2(self, phi):
+        return None if self.grad_scheme == "central" else self.ghost_pad_wide(phi, "phi", 2)
 
     # -- equilibria, sources, collision (S8-S10) --------------------------------
 
@@ -416,12 +476,26 @@ class Model:
         cs2 = L.cs2
         prod = m.rho * cs2 * self.rho_g * m.q * (1.0 / self.rho_g - 1.0 / self.rho_l)
         feq, S = [], []
+        biased = self.grad_scheme != "central"
+        if biased:
+            # R27: the projections on c_i of grad(rho) and of the surface
+            # tension use the biased directional derivative; u . X keeps the
+            # Eq. Grad vector
+            u_grho = sum(m.u[a] * m.grad_rho[a] for a in range(3))
+            u_F = sum(m.u[a] * m.F[a] for a in range(3))
+            Fn = [(m.rho - self.rho_l) * self.grav[a] + self.body[a] for a in range(3)]
         for i in range(L.Q):
             feq.append(L.w[i] * m.p + m.rho * cs2 * (Gm[i] - L.w[i]))
-            Ff = 0.0
-            for a in range(3):
-                Ff = Ff + (L.c[i][a] - m.u[a]) * ((Gm[i] - L.w[i]) * cs2 * m.grad_rho[a]
-                                                  + Gm[i] * m.F[a])
+            if biased:
+                cp = self.cproj(m, L.c[i])
+                c_grho = (self.rho_g - self.rho_l) * cp
+                c_F = m.mu * cp + sum(L.c[i][a] * Fn[a] for a in range(3) if L.c[i][a] != 0)
+                Ff = ((Gm[i] - L.w[i]) * cs2 * (c_grho - u_grho) + Gm[i] * (c_F - u_F))
+            else:
+                Ff = 0.0
+                for a in range(3):
+                    Ff = Ff + (L.c[i][a] - m.u[a]) * ((Gm[i] - L.w[i]) * cs2 * m.grad_rho[a]
+                                                      + Gm[i] * m.F[a])
             S.append(Ff + L.w[i] * prod)
         return feq, S
 
@@ -601,7 +675,7 @@ class Model:
              else torch.zeros(self.shape, dtype=self.dt))
         zero = torch.zeros(self.shape, dtype=self.dt)
         m = Macros(phi, gphi, lphi, n, mu, rho, grho, F, u, zero, D, T, q, p, alpha,
-                   self.viscosity(phi))
+                   self.viscosity(phi), self._pad2(phi))
         f = g = s = None
         if self.ns:
             feq, S = self.f_terms(m)
