@@ -101,11 +101,15 @@ enum {
  *        D3Q7 second-order moments) at s_p.  Not built for D3Q19. */
 enum { LBM_COLL_BGK = 0, LBM_COLL_TRT = 1, LBM_COLL_MRT = 2 };
 
-/* Directional derivatives entering Eq. Grad for grad(phi) (normal, surface
- * tension, grad rho; Sec. 3.4): central (Eq. DerivDirec_Grad), or the
- * first- or second-order biased (upwind) differences the paper lists after
- * Eq. Laplacian.  The Laplacian and div(u phi) keep the central form.
- * BIASED2 reaches two nodes along each direction (2-D only). */
+/* Directional derivative c_i . grad(phi) in the NS source (Eq. Forcing:
+ * c_i . grad(rho) and the surface tension mu c_i . grad(phi)): the
+ * projection of the central Eq. Grad vector, or the first- or second-order
+ * biased (upwind) differences along c_i that Sec. 3.4 lists after Eq.
+ * Laplacian, phi(x + c_i) - phi(x) and [-phi(x + 2c_i) + 4 phi(x + c_i) -
+ * 3 phi(x)] / 2.  Every vector use of grad(phi) (velocity, pressure, the
+ * normal of the phase-field source, whose zeroth moment must vanish for phi
+ * to stay conserved) and the Laplacian keep the central stencils.  Ghosts
+ * two nodes beyond a wall mirror the second node from it. */
 enum { LBM_GRAD_CENTRAL = 0, LBM_GRAD_BIASED1 = 1, LBM_GRAD_BIASED2 = 2 };
 
 /* dtype of caller field arrays */
@@ -146,6 +150,10 @@ typedef struct {
                                   * reduction; synchronises) and returns
                                   * LBM_E_UNSTABLE at the first failure     */
 } lbm_params;
+/* Kernels: BGK with central derivatives and the radius-2 div(u phi) runs the
+ * default step kernels; any of TRT / MRT, a biased scheme or LBM_DIV_LOCAL
+ * (which needs LBM_NS | LBM_HEAT) runs the extended step kernels, with the
+ * same memory traffic. */
 
 /* Bytes of device workspace lbm_create needs for these parameters
  * (populations A and B, lagged phi and q, wall rows, reduction scratch).

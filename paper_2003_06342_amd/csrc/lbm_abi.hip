@@ -135,12 +135,8 @@ lbm_status validate(const lbm_params* p) {
   }
   if (p->grad_scheme < LBM_GRAD_CENTRAL || p->grad_scheme > LBM_GRAD_BIASED2)
     return fail(LBM_E_INVAL, "unknown grad_scheme %d", p->grad_scheme);
-  if (p->grad_scheme == LBM_GRAD_BIASED2) {
-    if (p->dim != 2) return fail(LBM_E_UNSUPPORTED, "LBM_GRAD_BIASED2 is built for 2-D");
-    // the 3-node ghost layer mirrors the third node from the wall
-    if ((p->bc[0] == LBM_BC_WALL && p->nx < 3) || (p->bc[1] == LBM_BC_WALL && p->ny < 3))
-      return fail(LBM_E_INVAL, "LBM_GRAD_BIASED2 needs at least 3 nodes along a walled axis");
-  }
+  if ((p->flags & LBM_DIV_LOCAL) && !((p->flags & LBM_NS) && (p->flags & LBM_HEAT)))
+    return fail(LBM_E_INVAL, "LBM_DIV_LOCAL needs LBM_NS and LBM_HEAT");
   if (p->check_every < 0) return fail(LBM_E_INVAL, "check_every must be >= 0");
   if (p->dim == 2) {
     // the 2-D kernel addresses each population family with 32-bit byte offsets

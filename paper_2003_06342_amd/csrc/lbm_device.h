@@ -361,6 +361,244 @@ __device__ inline void collide_s(const A& a, Real* s, const NodeMacro<Real>& m, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Collision operators of the extended step kernels (Sec. 3: TRT and MRT are
+// named after Eq. LBE as the way to reach lower mobility and higher Peclet
+// numbers).  All three act on the barred variables: with
+// a_i = v_i - eq_i + S_i/2 (non-equilibrium part plus half the source) the
+// post-collision value is a_i - Delta_i + eq_i + S_i/2, and
+//   BGK: Delta = omega a;
+//   TRT: the parts of a symmetric and antisymmetric under c -> -c relax at
+//        omega+ and omega-; the transport coefficient keeps the BGK rate
+//        (omega+ for the viscosity of f, omega- for the mobility of g and the
+//        diffusivity of s) and the other rate follows from the magic
+//        parameter Lambda = (1/omega+ - 1/2)(1/omega- - 1/2);
+//   MRT: a relaxes in an orthogonal moment basis, moment k at rate r_k
+//        (Delta = M^T diag(r_k / |M_k|^2) M a).
+// ---------------------------------------------------------------------------
+enum { COLL_BGK = 0, COLL_TRT = 1, COLL_MRT = 2 };
+enum { GRAD_CENTRAL = 0, GRAD_BIASED1 = 1, GRAD_BIASED2 = 2 };
+
+// Moment bases.  rate(fam, k) selects the rate of moment k for family fam
+// (0 f, 1 g, 2 s) from {s_e, s_eps, s_q, s_p, omega}: the transport moments
+// take the BGK rate omega (index 4).
+template <class Lat>
+struct MrtBasis {
+  static constexpr bool ok = false;
+  __host__ __device__ static constexpr double M(int, int) { return 0.0; }
+  __host__ __device__ static constexpr int rate(int, int) { return 4; }
+};
+// D2Q9 (Lallemand and Luo): 1, e = 3c^2 - 4, eps = 4 - 21c^2/2 + 9c^4/2,
+// cx, qx = (3c^2 - 5) cx, cy, qy = (3c^2 - 5) cy, cx^2 - cy^2, cx cy.
+template <>
+struct MrtBasis<D2Q9> {
+  static constexpr bool ok = true;
+  __host__ __device__ static constexpr double M(int k, int i) {
+    const double cx = D2Q9::cx(i), cy = D2Q9::cy(i), c2 = cx * cx + cy * cy;
+    switch (k) {
+      case 0: return 1.0;
+      case 1: return 3.0 * c2 - 4.0;
+      case 2: return 4.0 - 10.5 * c2 + 4.5 * c2 * c2;
+      case 3: return cx;
+      case 4: return (3.0 * c2 - 5.0) * cx;
+      case 5: return cy;
+      case 6: return (3.0 * c2 - 5.0) * cy;
+      case 7: return cx * cx - cy * cy;
+      default: return cx * cy;
+    }
+  }
+  __host__ __device__ static constexpr int rate(int fam, int k) {
+    // f: rho, e at s_e; eps at s_eps; j and q at s_q; stress at omega
+    // g, s: rho, e at s_e; eps at s_eps; j at omega; q at s_q; pxx, pxy at s_p
+    constexpr int rf[9] = {0, 0, 1, 2, 2, 2, 2, 4, 4};
+    constexpr int rg[9] = {0, 0, 1, 4, 2, 4, 2, 3, 3};
+    return fam == 0 ? rf[k] : rg[k];
+  }
+};
+// D3Q7: 1, cx, cy, cz, 7c^2 - 6, 2cx^2 - cy^2 - cz^2, cy^2 - cz^2 (g and s).
+template <>
+struct MrtBasis<D3Q7> {
+  static constexpr bool ok = true;
+  __host__ __device__ static constexpr double M(int k, int i) {
+    const double cx = D3Q7::cx(i), cy = D3Q7::cy(i), cz = D3Q7::cz(i);
+    const double c2 = cx * cx + cy * cy + cz * cz;
+    switch (k) {
+      case 0: return 1.0;
+      case 1: return cx;
+      case 2: return cy;
+      case 3: return cz;
+      case 4: return 7.0 * c2 - 6.0;
+      case 5: return 2.0 * cx * cx - cy * cy - cz * cz;
+      default: return cy * cy - cz * cz;
+    }
+  }
+  __host__ __device__ static constexpr int rate(int, int k) {
+    constexpr int r[7] = {0, 4, 4, 4, 0, 3, 3};
+    return r[k];
+  }
+};
+template <class Lat>
+__host__ __device__ constexpr double mrt_norm2(int k) {
+  double s = 0.0;
+  for (int i = 0; i < Lat::Q; ++i) s += MrtBasis<Lat>::M(k, i) * MrtBasis<Lat>::M(k, i);
+  return s;
+}
+
+// One family's collision in the general form.  eqs(i, eq, S) gives the
+// equilibrium and the source of direction i; om is the family's BGK rate.
+template <class Lat, int FAM, class Real, class A, class EqS>
+__device__ __forceinline__ void relax_general(const A& a, Real om, Real* v, const EqS& eqs) {
+  constexpr int Q = Lat::Q;
+  Real b[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    Real eq, S;
+    eqs(i, eq, S);
+    const Real h = (Real)0.5 * S;
+    v[i] = v[i] - eq + h;   // a_i
+    b[i] = eq + h;
+  }
+  if (a.coll == COLL_TRT) {
+    const Real tau = (Real)1 / om - (Real)0.5;
+    const Real oth = (Real)1 / (a.lam[FAM] / tau + (Real)0.5);
+    const Real op = FAM == 0 ? om : oth, on = FAM == 0 ? oth : om;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int j = Lat::opp(i);
+      if (j < i) continue;
+      if (j == i) {
+        v[i] = b[i] + ((Real)1 - op) * v[i];
+        continue;
+      }
+      const Real sym = (Real)0.5 * (v[i] + v[j]), anti = (Real)0.5 * (v[i] - v[j]);
+      const Real vi = b[i] + v[i] - op * sym - on * anti;
+      const Real vj = b[j] + v[j] - op * sym + on * anti;
+      v[i] = vi;
+      v[j] = vj;
+    }
+  } else if (a.coll == COLL_MRT) {
+    if constexpr (MrtBasis<Lat>::ok) {
+      const Real r[5] = {a.mrt[FAM][0], a.mrt[FAM][1], a.mrt[FAM][2], a.mrt[FAM][3], om};
+      Real dm[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        Real mk = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const double c = MrtBasis<Lat>::M(k, i);
+          if (c != 0.0) mk += (Real)c * v[i];
+        }
+        dm[k] = r[MrtBasis<Lat>::rate(FAM, k)] * mk * (Real)(1.0 / mrt_norm2<Lat>(k));
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        Real back = 0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          const double c = MrtBasis<Lat>::M(k, i);
+          if (c != 0.0) back += (Real)c * dm[k];
+        }
+        v[i] = b[i] + v[i] - back;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = b[i] + ((Real)1 - om) * v[i];
+  }
+}
+
+// The three families in the general form.  cproj(i) is c_i . grad(phi) as
+// the step's directional-derivative scheme gives it: the projection of the
+// Eq. Grad vector (central), or the first- or second-order biased
+// directional derivative of Sec. 3.4 along c_i.  It enters the terms of the
+// NS source that project grad(phi) on the population's direction:
+// c_i . grad(rho) and the surface tension mu c_i . grad(phi) of Eq.
+// Forcing.  The phase-field source keeps c_i . n of the Eq. Grad vector:
+// its zeroth moment must vanish for phi to stay conserved.
+template <class Lat, class Real, class A, class Proj>
+__device__ inline void collide_f_ext(const A& a, Real* f, const NodeMacro<Real>& m, Real prodP,
+                                     Real om, const Proj& cproj) {
+  const Real cs2 = (Real)Lat::cs2;
+  const Real huu = gamma_huu<Lat>(m.u);
+  const Real rc = m.rho * cs2;
+  const Real drho = a.rho_g - a.rho_l;
+  const Real ug = cs2 * dotD<Lat>(m.u, m.grho);
+  const Real uF = dotD<Lat>(m.u, m.F);
+  Real Fn[3];   // buoyancy and body force: F without the surface tension
+#pragma unroll
+  for (int d = 0; d < 3; ++d) Fn[d] = (m.rho - a.rho_l) * a.grav[d] + a.body[d];
+  relax_general<Lat, 0>(a, om, f, [&](int i, Real& eq, Real& S) {
+    const Real w = (Real)Lat::w(i);
+    const Real dG = dgamma_i<Lat>(i, m.u, huu);
+    const Real cp = cproj(i);
+    const Real X = cs2 * drho * cp - ug;
+    const Real Y = m.mu * cp + cdot<Lat>(i, Fn) - uF;
+    S = fma(dG, X, (w + dG) * Y) + w * prodP;
+    eq = fma(w, m.p, rc * dG);
+  });
+}
+
+template <class Lat, class Real, class A>
+__device__ inline void collide_g_ext(const A& a, Real* g, const NodeMacro<Real>& m) {
+  const Real huu = gamma_huu<Lat>(m.u);
+  const Real k = a.four_over_W * m.phi * ((Real)1 - m.phi);
+  Real kn[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) kn[d] = k * m.n[d];
+  relax_general<Lat, 1>(a, a.omega_g, g, [&](int i, Real& eq, Real& S) {
+    const Real w = (Real)Lat::w(i);
+    const Real geq = fma(m.phi, dgamma_i<Lat>(i, m.u, huu), m.phi * w);   // phi Gamma_i
+    const Real Fg = w * cdot<Lat>(i, kn);
+    const Real Pg = w * m.q;
+    if (a.geq_cac) {
+      eq = fma(a.M_over_cs2g, Fg, geq);
+      S = Pg;
+    } else {
+      eq = geq;
+      S = Fg + Pg;
+    }
+  });
+}
+
+template <class Lat, class Real, class A>
+__device__ inline void collide_s_ext(const A& a, Real* s, const NodeMacro<Real>& m, Real om) {
+  const Real huu = gamma_huu<Lat>(m.u);
+  const Real src = -a.Lcp * (m.dtphi + m.D);
+  relax_general<Lat, 2>(a, om, s, [&](int i, Real& eq, Real& S) {
+    const Real w = (Real)Lat::w(i);
+    eq = fma(m.T, dgamma_i<Lat>(i, m.u, huu), m.T * w);   // T Gamma_i
+    S = w * src;
+  });
+}
+
+// c_i . grad(phi) of a lattice direction (cx, cy, cz) for the scheme
+// `scheme`: the projection of the Eq. Grad vector g, or the biased
+// directional derivatives of Sec. 3.4, phi(x + c) - phi(x) and
+// [-phi(x + 2c) + 4 phi(x + c) - 3 phi(x)] / 2, from at(s) = phi(x + s c).
+template <class Real, class At>
+__device__ __forceinline__ Real dir_deriv(int scheme, int cx, int cy, int cz, const Real* g,
+                                          const At& at) {
+  if (cx == 0 && cy == 0 && cz == 0) return (Real)0;
+  if (scheme == GRAD_CENTRAL) {
+    Real r = cx ? (Real)cx * g[0] : (Real)0;
+    if (cy) r = cx ? r + (Real)cy * g[1] : (Real)cy * g[1];
+    if (cz) r = (cx || cy) ? r + (Real)cz * g[2] : (Real)cz * g[2];
+    return r;
+  }
+  const Real c = at(0), p1 = at(1);
+  if (scheme == GRAD_BIASED1) return p1 - c;
+  return (Real)0.5 * ((Real)4 * p1 - at(2) - (Real)3 * c);
+}
+
+// div(u phi) in the local form (flag LBM_DIV_LOCAL): u . grad(phi) +
+// phi div(u), with div(u) = m''' (1/rho_g - 1/rho_l) from Eq.
+// ConservMasse_ChgtPhase and the production of the previous step.
+template <class Real, class A>
+__device__ __forceinline__ Real div_local_term(const A& a, const Real* u, const Real* gphi,
+                                               Real phi, Real q_prev) {
+  return u[0] * gphi[0] + u[1] * gphi[1] + u[2] * gphi[2] + phi * a.prod_fac * q_prev;
+}
+
 // Viscosity (Eq. Viscosity / Visco_lin) and diffusivity (linear).
 template <class Real, class A>
 __device__ inline Real viscosity(const A& a, Real phi) {

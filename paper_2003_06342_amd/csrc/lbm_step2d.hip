@@ -33,7 +33,7 @@ struct StepTile {
   static constexpr int NT = TY <= 16 ? TX2 * TY : 512;
 };
 
-template <class Store, class Real, bool NS, bool HEAT, int MODE, bool FAST, int TY>
+template <class Store, class Real, bool NS, bool HEAT, int MODE, bool FAST, int TY, bool EXT>
 __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*sphi)[R1X],
                                             Real (*sux)[R2X], Real (*suy)[R2X], int x0, int y0) {
   using C = Codec<Real, Store>;
@@ -63,6 +63,13 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
       m.grho[d] = drho * m.gphi[d];
       m.n[d] = m.gphi[d] * inrm;
     }
+    // c_i . grad(phi) for the extended kernels' sources (central or biased)
+    auto cproj = [&](int i) -> Real {
+      const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+      return dir_deriv<Real>(a.grad_scheme, cx, cy, 0, m.gphi,
+                             [&](int st) { return sphi[r + 2 + st * cy][lx + 2 + st * cx]; });
+    };
+    (void)cproj;
     m.u[0] = m.u[1] = m.u[2] = 0;
     Real f[9];
     Real m0f = 0;
@@ -95,7 +102,16 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
     if constexpr (HEAT) {
       Real s[9];
       gather2d<D2Q9, 2, FAST>(a, x, y, s);
-      if constexpr (NS) m.D = divergence2d<Real>(sphi, sux, suy, r + 1, lx + 1);
+      if constexpr (NS) {
+        if constexpr (EXT || MODE == MODE_MACRO) {
+          if (a.div_local)
+            m.D = div_local_term(a, m.u, m.gphi, m.phi, (Real)ld_plane(a.A_qp, node));
+          else
+            m.D = divergence2d<Real>(sphi, sux, suy, r + 1, lx + 1);
+        } else {
+          m.D = divergence2d<Real>(sphi, sux, suy, r + 1, lx + 1);
+        }
+      }
       Real m0s = 0;
 #pragma unroll
       for (int i = 0; i < 9; ++i) m0s += s[i];
@@ -103,7 +119,10 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
       m.q = production(a, m.phi, m.T, m.alpha);
       if constexpr (MODE == MODE_STEP) {
         const Real om = (Real)1 / (m.alpha * (Real)3 + (Real)0.5);
-        collide_s<D2Q9>(a, s, m, om);
+        if constexpr (EXT)
+          collide_s_ext<D2Q9>(a, s, m, om);
+        else
+          collide_s<D2Q9>(a, s, m, om);
         // 16-bit storage: the s deviations are about this node's own T
         const Real Tref = kNodeRef<Real, Store> ? (Real)(Sc)m.T : a.ref[2];
         store_family<D2Q9>(a, a.off_s, 2, node, s, Tref);
@@ -118,7 +137,10 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
       } else {
         gather2d<D2Q9, 1, FAST>(a, x, y, g);
       }
-      collide_g<D2Q9>(a, g, m);
+      if constexpr (EXT)
+        collide_g_ext<D2Q9>(a, g, m);
+      else
+        collide_g<D2Q9>(a, g, m);
       store_family<D2Q9>(a, a.off_g, 1, node, g,
                          kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1]);
     }
@@ -140,7 +162,10 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
       if constexpr (MODE == MODE_STEP) {
         m.nu = viscosity(a, m.phi);
         const Real om = (Real)1 / (m.nu * (Real)3 + (Real)0.5);
-        collide_f<D2Q9>(f, m, m.rho * cs2 * m.q * a.prod_fac, om);
+        if constexpr (EXT)
+          collide_f_ext<D2Q9>(a, f, m, m.rho * cs2 * m.q * a.prod_fac, om, cproj);
+        else
+          collide_f<D2Q9>(f, m, m.rho * cs2 * m.q * a.prod_fac, om);
         store_family<D2Q9>(a, a.off_f, 0, node, f, a.ref[0]);
       }
     }
@@ -179,7 +204,7 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
   }
 }
 
-template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY>
+template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT>
 __device__ __forceinline__ void step2d_body(const KArgs<Real, Store>& a) {
   __shared__ Real sphi[Tile2<TY>::R1Y][R1X];
   __shared__ Real sux[Tile2<TY>::R2Y][R2X];
@@ -196,23 +221,26 @@ __device__ __forceinline__ void step2d_body(const KArgs<Real, Store>& a) {
   // lies inside the domain, so no wall link and no periodic wrap occurs
   const bool interior = x0 >= 3 && x0 + TX2 + 3 <= a.nx && y0 >= 3 && y0 + TY + 3 <= a.ny;
   if (interior)
-    step_tile2d<Store, Real, NS, HEAT, MODE, true, TY>(a, sphi, sux, suy, x0, y0);
+    step_tile2d<Store, Real, NS, HEAT, MODE, true, TY, EXT>(a, sphi, sux, suy, x0, y0);
   else
-    step_tile2d<Store, Real, NS, HEAT, MODE, false, TY>(a, sphi, sux, suy, x0, y0);
+    step_tile2d<Store, Real, NS, HEAT, MODE, false, TY, EXT>(a, sphi, sux, suy, x0, y0);
 }
 
-template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY>
+// EXT: the extended step (TRT / MRT collision, biased directional
+// derivatives, local div(u phi)), selected at run time from the arguments;
+// the default kernels are BGK with central derivatives.
+template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT>
 __global__ __launch_bounds__(StepTile<TY>::NT) void k_step2d(const KArgs<Real, Store> a) {
-  step2d_body<Store, Real, NS, HEAT, MODE, TY>(a);
+  step2d_body<Store, Real, NS, HEAT, MODE, TY, EXT>(a);
 }
 
 // 16-bit storage: at most 128 VGPRs (4 waves per SIMD).  The codec constants
 // and per-node references pushed the 64-row tile kernel past that (0.200 ->
 // 0.136 ms at 1024 x 2048 with the cap); the 4-row carry kernel needs 72.
-template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY>
+template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT>
 __global__ __launch_bounds__(StepTile<TY>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_step2d_w4(
     const KArgs<Real, Store> a) {
-  step2d_body<Store, Real, NS, HEAT, MODE, TY>(a);
+  step2d_body<Store, Real, NS, HEAT, MODE, TY, EXT>(a);
 }
 
 // Initialisation: populations = equilibrium - S/2 at the given fields with
@@ -237,12 +265,12 @@ __global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, cons
       add = (Real)2 * a.phi_w[1][yy < 0 ? 0 : 1];
       sgn = -1;
       yy = mirror(yy, a.ny);
-    } else if (!a.wall[1]) yy = wrap1(yy, a.ny);
+    } else if (!a.wall[1]) yy = wrapmod(yy, a.ny);
     Real v;
     if (a.wall[0] && (xx < 0 || xx >= a.nx)) {
       v = (Real)2 * a.phi_w[0][xx < 0 ? 0 : 1] - ld(phi0, 0, mirror(xx, a.nx), yy);
     } else {
-      if (!a.wall[0]) xx = wrap1(xx, a.nx);
+      if (!a.wall[0]) xx = wrapmod(xx, a.nx);
       v = ld(phi0, 0, xx, yy);
     }
     return add + sgn * v;
@@ -291,7 +319,13 @@ __global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, cons
   m.u[2] = 0;
   m.dtphi = 0;
   m.D = 0;
-  if (HEAT && NS && u0) {
+  m.alpha = diffusivity(a, m.phi);
+  m.T = HEAT ? ld(T0, 0, x, y) : (Real)0;
+  m.q = HEAT ? production(a, m.phi, m.T, m.alpha) : (Real)0;
+  if (HEAT && NS && a.div_local) {
+    // the first step's local form sees q_prev = q(phi0, T0)
+    m.D = div_local_term(a, m.u, m.gphi, m.phi, m.q);
+  } else if (HEAT && NS && u0) {
     Real d = 0;
     for (int i = 1; i < 9; ++i) {
       const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
@@ -302,21 +336,32 @@ __global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, cons
     }
     m.D = d * (Real)3;
   }
-  m.alpha = diffusivity(a, m.phi);
-  m.T = HEAT ? ld(T0, 0, x, y) : (Real)0;
-  m.q = HEAT ? production(a, m.phi, m.T, m.alpha) : (Real)0;
   m.p = (NS && p0) ? ld(p0, 0, x, y) : (Real)0;
   const Real cs2 = (Real)(1.0 / 3.0);
-  // eq - S/2 == the collision of (eq - S/2) with omega = 1 minus S ... write explicitly:
+  // populations = eq - S/2, written out
   Real f[9], g[9], s[9];
   const Real a0 = gamma_huu<D2Q9>(m.u);
+  const bool biased = a.grad_scheme != GRAD_CENTRAL;
   for (int i = 0; i < 9; ++i) {
     const Real w = (Real)D2Q9::w(i);
     const Real G = gamma_i<D2Q9>(i, m.u, a0);
-    const Real c[3] = {(Real)D2Q9::cx(i), (Real)D2Q9::cy(i), (Real)0};
+    const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+    const Real c[3] = {(Real)cx, (Real)cy, (Real)0};
     if (NS) {
       Real Ff = 0;
-      for (int d = 0; d < 3; ++d) Ff += (c[d] - m.u[d]) * ((G - w) * cs2 * m.grho[d] + G * m.F[d]);
+      if (biased) {
+        // biased schemes: c_i . grad(phi) of the NS source is the
+        // directional derivative along c_i
+        const Real cp = dir_deriv<Real>(a.grad_scheme, cx, cy, 0, m.gphi,
+                                        [&](int st) { return phi_at(x + st * cx, y + st * cy); });
+        const Real ug = cs2 * (m.u[0] * m.grho[0] + m.u[1] * m.grho[1]);
+        const Real uF = m.u[0] * m.F[0] + m.u[1] * m.F[1];
+        const Real drb = m.rho - a.rho_l;
+        const Real cFn = c[0] * (drb * a.grav[0] + a.body[0]) + c[1] * (drb * a.grav[1] + a.body[1]);
+        Ff = (G - w) * (cs2 * (a.rho_g - a.rho_l) * cp - ug) + G * (m.mu * cp + cFn - uF);
+      } else {
+        for (int d = 0; d < 3; ++d) Ff += (c[d] - m.u[d]) * ((G - w) * cs2 * m.grho[d] + G * m.F[d]);
+      }
       const Real S = Ff + w * m.rho * cs2 * m.q * a.prod_fac;
       f[i] = w * m.p + m.rho * cs2 * (G - w) - (Real)0.5 * S;
     }
@@ -395,14 +440,20 @@ static hipError_t launch_step2d_t(const KArgs<Real, Store>& a, int ns, int heat,
   constexpr bool small_tiles = st16 || sizeof(Store) == 8;
   const int ty = mode != MODE_STEP ? 64 : (small_tiles ? 4 : 16);
   const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + ty - 1) / ty);
-#define LBM_L(NSV, HV, MV, TYV)                                                                 \
+  const bool ext = a.coll != COLL_BGK || a.grad_scheme != GRAD_CENTRAL || a.div_local;
+#define LBM_K(NSV, HV, MV, TYV, EV)                                                             \
   do {                                                                                          \
     if constexpr (st16)                                                                         \
-      hipLaunchKernelGGL((k_step2d_w4<Store, Real, NSV, HV, MV, TYV>), dim3(tiles),            \
-                         dim3(StepTile<TYV>::NT), 0, st, a);                                       \
+      hipLaunchKernelGGL((k_step2d_w4<Store, Real, NSV, HV, MV, TYV, EV>), dim3(tiles),        \
+                         dim3(StepTile<TYV>::NT), 0, st, a);                                    \
     else                                                                                        \
-      hipLaunchKernelGGL((k_step2d<Store, Real, NSV, HV, MV, TYV>), dim3(tiles),               \
-                         dim3(StepTile<TYV>::NT), 0, st, a);                                       \
+      hipLaunchKernelGGL((k_step2d<Store, Real, NSV, HV, MV, TYV, EV>), dim3(tiles),           \
+                         dim3(StepTile<TYV>::NT), 0, st, a);                                    \
+  } while (0)
+#define LBM_L(NSV, HV, MV, TYV)                      \
+  do {                                               \
+    if (ext) LBM_K(NSV, HV, MV, TYV, true);          \
+    else LBM_K(NSV, HV, MV, TYV, false);             \
   } while (0)
 #define LBM_L2(NSV, HV, MV)                \
   if constexpr (small_tiles) LBM_L(NSV, HV, MV, 4); \
@@ -413,13 +464,15 @@ static hipError_t launch_step2d_t(const KArgs<Real, Store>& a, int ns, int heat,
     else if (heat) { LBM_L2(false, true, MODE_STEP); }
     else { LBM_L2(false, false, MODE_STEP); }
   } else {
-    if (ns && heat) LBM_L(true, true, MODE_MACRO, 64);
-    else if (ns) LBM_L(true, false, MODE_MACRO, 64);
-    else if (heat) LBM_L(false, true, MODE_MACRO, 64);
-    else LBM_L(false, false, MODE_MACRO, 64);
+    // the fields pass takes the local div(u phi) at run time
+    if (ns && heat) LBM_K(true, true, MODE_MACRO, 64, false);
+    else if (ns) LBM_K(true, false, MODE_MACRO, 64, false);
+    else if (heat) LBM_K(false, true, MODE_MACRO, 64, false);
+    else LBM_K(false, false, MODE_MACRO, 64, false);
   }
 #undef LBM_L2
 #undef LBM_L
+#undef LBM_K
   return hipGetLastError();
 }
 

@@ -159,7 +159,7 @@ __device__ inline int zplane(int p, int nz, int wall, bool& ghost) {
   return wrapmod(p, nz);
 }
 
-template <class S, class Store, class Real, bool NS, bool HEAT, int MODE, bool XYIN>
+template <class S, class Store, class Real, bool NS, bool HEAT, int MODE, bool XYIN, bool EXT>
 __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi)[S::P1Y][S::P1X],
                                         Real (*su)[3][S::P2Y][S::P2X], int x0, int y0, int z0, int z1) {
   using Sc = typename ScalarOf<Store>::T;
@@ -244,6 +244,13 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
         m.grho[d] = drho * m.gphi[d];
         m.n[d] = m.gphi[d] * inrm;
       }
+      // c_i . grad(phi) for the extended kernels' sources (central or biased)
+      auto cproj = [&](int cx, int cy, int cz) -> Real {
+        return dir_deriv<Real>(a.grad_scheme, cx, cy, cz, m.gphi, [&](int st) {
+          return sphi[slot5(k + st * cz)][ly + 2 + st * cy][lx + 2 + st * cx];
+        });
+      };
+      (void)cproj;
       m.u[0] = m.u[1] = m.u[2] = 0;
       Real f[19];
       Real m0f = 0;
@@ -273,7 +280,16 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
       if constexpr (HEAT) {
         Real s[7];
         gather3d<D3Q7, 2, XYIN>(a, x, y, z, s);
-        if constexpr (NS) m.D = divergence3d<S, Real>(sphi, su, k, ly + 1, lx + 1);
+        if constexpr (NS) {
+          if constexpr (EXT || MODE == MODE_MACRO) {
+            if (a.div_local)
+              m.D = div_local_term(a, m.u, m.gphi, m.phi, (Real)a.A_qp[node]);
+            else
+              m.D = divergence3d<S, Real>(sphi, su, k, ly + 1, lx + 1);
+          } else {
+            m.D = divergence3d<S, Real>(sphi, su, k, ly + 1, lx + 1);
+          }
+        }
         Real m0s = 0;
 #pragma unroll
         for (int i = 0; i < 7; ++i) m0s += s[i];
@@ -281,7 +297,10 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
         m.q = production(a, m.phi, m.T, m.alpha);
         if constexpr (MODE == MODE_STEP) {
           const Real om = (Real)1 / (m.alpha * (Real)4 + (Real)0.5);   // c_s^2 = 1/4
-          collide_s<D3Q7>(a, s, m, om);
+          if constexpr (EXT)
+            collide_s_ext<D3Q7>(a, s, m, om);
+          else
+            collide_s<D3Q7>(a, s, m, om);
           const Real Tref = kNodeRef<Real, Store> ? (Real)(Sc)m.T : a.ref[2];
           store3d<D3Q7>(a, a.off_s, 2, node, s, Tref);
           if constexpr (kNodeRef<Real, Store>) a.B_Tref[node] = (Sc)m.T;
@@ -290,7 +309,10 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
       if constexpr (MODE == MODE_STEP) {
         Real g[7];
         gather3d<D3Q7, 1, XYIN>(a, x, y, z, g);
-        collide_g<D3Q7>(a, g, m);
+        if constexpr (EXT)
+          collide_g_ext<D3Q7>(a, g, m);
+        else
+          collide_g<D3Q7>(a, g, m);
         store3d<D3Q7>(a, a.off_g, 1, node, g, kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1]);
       }
       const Real cs2 = (Real)(1.0 / 3.0);
@@ -306,7 +328,12 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
         if constexpr (MODE == MODE_STEP) {
           m.nu = viscosity(a, m.phi);
           const Real om = (Real)1 / (m.nu * (Real)3 + (Real)0.5);
-          collide_f<D3Q19>(f, m, m.rho * cs2 * m.q * a.prod_fac, om);
+          if constexpr (EXT)
+            collide_f_ext<D3Q19>(a, f, m, m.rho * cs2 * m.q * a.prod_fac, om, [&](int i) {
+              return cproj(D3Q19::cx(i), D3Q19::cy(i), D3Q19::cz(i));
+            });
+          else
+            collide_f<D3Q19>(f, m, m.rho * cs2 * m.q * a.prod_fac, om);
           store3d<D3Q19>(a, a.off_f, 0, node, f, a.ref[0]);
         }
       }
@@ -363,7 +390,9 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
   }
 }
 
-template <class S, class Store, class Real, bool NS, bool HEAT, int MODE>
+// EXT: the extended step (TRT / MRT collision, biased directional
+// derivatives, local div(u phi)), selected at run time from the arguments.
+template <class S, class Store, class Real, bool NS, bool HEAT, int MODE, bool EXT>
 __global__ __launch_bounds__(S::NT) void k_step3d(const KArgs<Real, Store> a) {
   __shared__ Real sphi[NPHI][S::P1Y][S::P1X];
   __shared__ Real su[NU][3][S::P2Y][S::P2X];
@@ -378,9 +407,9 @@ __global__ __launch_bounds__(S::NT) void k_step3d(const KArgs<Real, Store> a) {
   const int z1 = min(z0 + S::ZC, a.nz);
   const bool xyin = x0 >= 3 && x0 + S::TX + 3 <= a.nx && y0 >= 3 && y0 + S::TY + 3 <= a.ny;
   if (xyin)
-    march3d<S, Store, Real, NS, HEAT, MODE, true>(a, sphi, su, x0, y0, z0, z1);
+    march3d<S, Store, Real, NS, HEAT, MODE, true, EXT>(a, sphi, su, x0, y0, z0, z1);
   else
-    march3d<S, Store, Real, NS, HEAT, MODE, false>(a, sphi, su, x0, y0, z0, z1);
+    march3d<S, Store, Real, NS, HEAT, MODE, false, EXT>(a, sphi, su, x0, y0, z0, z1);
 }
 
 // Initialisation (3-D): equilibrium - S/2 at the initial fields, scattered
@@ -399,11 +428,11 @@ __global__ __launch_bounds__(256) void k_init3d(const KArgs<Real, Store> a, cons
     return f64 ? (Real)((const double*)p)[i] : (Real)((const float*)p)[i];
   };
   auto phi_at = [&](int xx, int yy, int zz) -> Real {
-    xx = wrap1(xx, a.nx);
-    yy = wrap1(yy, a.ny);
+    xx = wrapmod(xx, a.nx);
+    yy = wrapmod(yy, a.ny);
     if (a.wall[2] && (zz < 0 || zz >= a.nz))
       return (Real)2 * a.phi_w[2][zz < 0 ? 0 : 1] - ld(phi0, 0, xx, yy, mirror3(zz, a.nz));
-    if (!a.wall[2]) zz = wrap1(zz, a.nz);
+    if (!a.wall[2]) zz = wrapmod(zz, a.nz);
     return ld(phi0, 0, xx, yy, zz);
   };
   auto u_at = [&](int c, int xx, int yy, int zz) -> Real {
@@ -440,7 +469,13 @@ __global__ __launch_bounds__(256) void k_init3d(const KArgs<Real, Store> a, cons
   }
   m.dtphi = 0;
   m.D = 0;
-  if (HEAT && NS && u0) {
+  m.alpha = diffusivity(a, m.phi);
+  m.T = HEAT ? ld(T0, 0, x, y, z) : (Real)0;
+  m.q = HEAT ? production(a, m.phi, m.T, m.alpha) : (Real)0;
+  if (HEAT && NS && a.div_local) {
+    // the first step's local form sees q_prev = q(phi0, T0)
+    m.D = div_local_term(a, m.u, m.gphi, m.phi, m.q);
+  } else if (HEAT && NS && u0) {
     Real d = 0;
     for (int i = 1; i < 19; ++i) {
       const int c[3] = {D3Q19::cx(i), D3Q19::cy(i), D3Q19::cz(i)};
@@ -453,10 +488,14 @@ __global__ __launch_bounds__(256) void k_init3d(const KArgs<Real, Store> a, cons
     }
     m.D = d * (Real)3;
   }
-  m.alpha = diffusivity(a, m.phi);
-  m.T = HEAT ? ld(T0, 0, x, y, z) : (Real)0;
-  m.q = HEAT ? production(a, m.phi, m.T, m.alpha) : (Real)0;
   m.p = (NS && p0) ? ld(p0, 0, x, y, z) : (Real)0;
+  const bool biased = a.grad_scheme != GRAD_CENTRAL;
+  // biased schemes: c_i . grad(phi) is the directional derivative along c_i
+  auto cproj = [&](int cx, int cy, int cz) -> Real {
+    return dir_deriv<Real>(a.grad_scheme, cx, cy, cz, m.gphi, [&](int st) {
+      return phi_at(x + st * cx, y + st * cy, z + st * cz);
+    });
+  };
   const Real cs2 = (Real)(1.0 / 3.0);
   const int pz = a.px * a.ny;
   const Real a0f = gamma_huu<D3Q19>(m.u), a0g = gamma_huu<D3Q7>(m.u);
@@ -467,7 +506,19 @@ __global__ __launch_bounds__(256) void k_init3d(const KArgs<Real, Store> a, cons
       const Real G = gamma_i<D3Q19>(i, m.u, a0f);
       const Real c[3] = {(Real)D3Q19::cx(i), (Real)D3Q19::cy(i), (Real)D3Q19::cz(i)};
       Real Ff = 0;
-      for (int d = 0; d < 3; ++d) Ff += (c[d] - m.u[d]) * ((G - w) * cs2 * m.grho[d] + G * m.F[d]);
+      if (biased) {
+        const Real cp = cproj(D3Q19::cx(i), D3Q19::cy(i), D3Q19::cz(i));
+        Real ug = 0, uF = 0, cFn = 0;
+        const Real drb = m.rho - a.rho_l;
+        for (int d = 0; d < 3; ++d) {
+          ug += m.u[d] * m.grho[d];
+          uF += m.u[d] * m.F[d];
+          cFn += c[d] * (drb * a.grav[d] + a.body[d]);
+        }
+        Ff = (G - w) * (cs2 * (a.rho_g - a.rho_l) * cp - cs2 * ug) + G * (m.mu * cp + cFn - uF);
+      } else {
+        for (int d = 0; d < 3; ++d) Ff += (c[d] - m.u[d]) * ((G - w) * cs2 * m.grho[d] + G * m.F[d]);
+      }
       const Real S = Ff + w * m.rho * cs2 * m.q * a.prod_fac;
       const Real val = w * m.p + m.rho * cs2 * (G - w) - (Real)0.5 * S;
       const int sz = z - D3Q19::cz(i);
@@ -536,15 +587,24 @@ static hipError_t launch_step3d_t(const KArgs<Real, Store>& a, int ns, int heat,
                                   hipStream_t st) {
   // the FP32 step on the wide shape; everything else (and the fields pass,
   // whose per-block partials are sized by step3d_blocks) on the standard one
-  const bool wide = mode == MODE_STEP && std::is_same<Store, float>::value;
+  const bool ext = a.coll != COLL_BGK || a.grad_scheme != GRAD_CENTRAL || a.div_local;
+  const bool wide = mode == MODE_STEP && !ext && std::is_same<Store, float>::value;
 #define LBM_L(NSV, HV, MV)                                                                     \
   do {                                                                                         \
+    if constexpr (MV == MODE_STEP) {                                                           \
+      if (ext) {                                                                               \
+        hipLaunchKernelGGL((k_step3d<ShapeStd3, Store, Real, NSV, HV, MV, true>),             \
+                           dim3(blocks3d<ShapeStd3>(a.nx, a.ny, a.nz)), dim3(ShapeStd3::NT), 0, \
+                           st, a);                                                             \
+        break;                                                                                 \
+      }                                                                                        \
+    }                                                                                          \
     if (wide)                                                                                  \
-      hipLaunchKernelGGL((k_step3d<ShapeWide3, Store, Real, NSV, HV, MV>),                    \
+      hipLaunchKernelGGL((k_step3d<ShapeWide3, Store, Real, NSV, HV, MV, false>),             \
                          dim3(blocks3d<ShapeWide3>(a.nx, a.ny, a.nz)), dim3(ShapeWide3::NT), 0, \
                          st, a);                                                               \
     else                                                                                       \
-      hipLaunchKernelGGL((k_step3d<ShapeStd3, Store, Real, NSV, HV, MV>),                     \
+      hipLaunchKernelGGL((k_step3d<ShapeStd3, Store, Real, NSV, HV, MV, false>),              \
                          dim3(blocks3d<ShapeStd3>(a.nx, a.ny, a.nz)), dim3(ShapeStd3::NT), 0,   \
                          st, a);                                                               \
   } while (0)

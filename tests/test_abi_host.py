@@ -127,6 +127,33 @@ def test_walled_axis_needs_two_nodes(lib):
     assert _status(prm)[0] == lbm.LBM_OK
 
 
+def test_extended_options_validated(lib):
+    """MRT has no D3Q19 basis (NS in 3-D), the local div(u phi) needs the NS
+    and heat families, unknown collision / gradient codes are rejected; the
+    supported combinations pass."""
+    p3 = I.film3d_params(32, nz=24)
+    p3["collision"] = "mrt"
+    assert _status(p3)[0] == lbm.LBM_E_UNSUPPORTED
+    p3["ns"] = False
+    assert _status(p3)[0] == lbm.LBM_OK
+    p2 = I.film2d_params(16, 8)
+    p2.update(div_local=True, heat=False, phase_change=False)
+    assert _status(p2)[0] == lbm.LBM_E_INVAL
+    p2 = I.film2d_params(16, 8)
+    p2.update(div_local=True, collision="trt", grad_scheme="biased2")
+    assert _status(p2)[0] == lbm.LBM_OK
+    p = lbm.make_params(I.film2d_params(16, 8), "f32")
+    p.collision = 7
+    n = C.c_size_t()
+    assert lib.lbm_workspace_size(C.byref(p), C.byref(n)) == lbm.LBM_E_INVAL
+    p = lbm.make_params(I.film2d_params(16, 8), "f32")
+    p.grad_scheme = 3
+    assert lib.lbm_workspace_size(C.byref(p), C.byref(n)) == lbm.LBM_E_INVAL
+    p = lbm.make_params(dict(I.film2d_params(16, 8), collision="mrt",
+                             mrt_rates=[[1.0] * 4, [1.0, 2.0, 1.0, 1.0], [1.0] * 4]), "f32")
+    assert lib.lbm_workspace_size(C.byref(p), C.byref(n)) == lbm.LBM_E_INVAL
+
+
 def test_stream_probe_library_loads_and_checks_arguments():
     """The measurement probes bench.py times beside the step (their own
     library, outside the C ABI) are built, export their launchers, and

@@ -132,13 +132,31 @@ def test_adjoint_sqrtT_segments_match_oracle():
     assert e_phi < 1e-9 and e_tw < 1e-9
 
 
+def _fp32_floor(n):
+    """FP32 rounding floor of this check (the oracle's reverse pass in
+    float32 against float64 on the same recipe and directions), written by
+    tests/golden/make_adjoint_fp32_floor.py from the oracle only."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "adjoint_fp32_floor.json")
+    rec = json.load(open(path)).get(str(n)) if os.path.exists(path) else None
+    if rec is None:
+        pytest.fail(f"no FP32 floor for {n} steps in {path}")
+    return rec
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("n,bar", [(300, 1e-4), (1000, 1e-4)])
 def test_adjoint_vs_central_fd_config4_size(n, bar, storage):
     """512 x 512 film (lambda = 512 gravity, h = 32 + 2 cos + noise, T_w ~
-    N(1, 0.05^2)), FP64: directional derivatives of V along 16 random unit
-    directions of T_w and of phi0 vs central differences (step 1e-4),
-    compared as the relative L2 error over the 16 directions of each kind.
+    N(1, 0.05^2)): directional derivatives of V from the FP64 or FP32
+    adjoint along 16 random unit directions of T_w and of phi0 vs central
+    differences of the FP64 forward (step 1e-4), compared as the relative L2
+    error over the 16 directions of each kind.  The T_w sensitivity of this
+    film is small and fragile: the oracle's own reverse pass evaluated in
+    float32 departs from float64 by about 2e-3 on it, so the FP32 bar is the
+    larger of 1e-4 and 3 x that floor.
 
     The film's sensitivities grow by about 1e3 between steps 1000 and 2000
     (the vapour-side sharpening regime), and rounding of the FP64 forward is
@@ -178,11 +196,16 @@ def test_adjoint_vs_central_fd_config4_size(n, bar, storage):
             say(f"[adjoint] n={n} dir {k} {kind}: fd {fd:.10e} adj {ad:.10e} "
                 f"rel {abs(fd - ad) / max(abs(fd), 1e-300):.2e}")
     # relative L2 over the 16 directions: a direction along which V barely
-    # changes carries the difference quotient's absolute error only
+    # changes carries the difference quotient's absolute error only.  FP32
+    # storage: the bar is also at least 3 x the FP32 floor of the same metric
+    # (the oracle's own reverse pass in float32 against float64)
+    floor = _fp32_floor(n) if storage == "f32" else {"Tw": 0.0, "phi0": 0.0}
     for kind in ("Tw", "phi0"):
         e = rel_l2(ads[kind], fds[kind])
-        say(f"[adjoint] n={n} {storage} {kind}: relative L2 over 16 directions {e:.2e}")
-        assert e <= bar, (kind, e)
+        b = max(bar, 3.0 * floor[kind])
+        say(f"[adjoint] n={n} {storage} {kind}: relative L2 over 16 directions {e:.2e} "
+            f"(bar {b:.1e}, fp32 floor {floor[kind]:.1e})")
+        assert e <= b, (kind, e, floor[kind])
 
 
 def _oracle_grads(prm, phi0, T0, Tw, n, loss, dtype=F64):
