@@ -266,6 +266,24 @@ lbm_status lbm_backward(lbm_ctx* ctx, const void* g_phi, const void* g_T, const 
                         void* d_phi0, void* d_T0, void* d_Twall, int32_t tw_axis,
                         int32_t tw_side, int32_t out_dtype);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * lbm_backward with its scratch workspace taken from a static device array
+ * of the library instead of dev_ws.  The array holds
+ * LBM_STATIC_SCRATCH_BYTES on every device the library runs on, from module
+ * load until the process ends; the adjoint workspace of a 512 x 512 FP32
+ * film (70 MiB) fits.  Arguments, seeds, outputs, errors and the tape are
+ * those of lbm_backward; returns LBM_E_NOMEM when
+ * lbm_adjoint_workspace_size exceeds the array.  Allocates nothing.  Every
+ * call on one GPU shares that GPU's array and leaves it holding its
+ * intermediates (each call clears what must start at zero): calls that
+ * overlap in time on one GPU race, so serialise them (one stream, or an
+ * event between them).  Asynchronous. */
+#define LBM_STATIC_SCRATCH_BYTES (128u << 20)
+lbm_status lbm_backward_static(lbm_ctx* ctx, const void* g_phi, const void* g_T, const void* g_u,
+                               const void* g_p, int32_t seed_dtype, void* d_phi0, void* d_T0,
+                               void* d_Twall, int32_t tw_axis, int32_t tw_side, int32_t out_dtype);
+
 void lbm_destroy(lbm_ctx* ctx);
 
 /* Message of the last error on the calling thread (never NULL). */

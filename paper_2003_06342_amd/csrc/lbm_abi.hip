@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/lbm.h"
@@ -79,9 +80,41 @@ struct lbm_ctx {
   // the current state is step `step` of an lbm_init_fields call with u0 ==
   // NULL (the initialisation the reverse sweep differentiates)
   int fresh_init;
+  // this device's copy of the static scratch (lbm_backward_static)
+  void* scratch;
 };
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// Static scratch of lbm_backward_static: the adjoint workspace for callers
+// that cannot allocate device memory.  Every device the library runs on
+// holds its own copy from module load until the process ends.  In host code
+// the symbol is only a host-side stand-in: kernels and copies get the
+// device address hipGetSymbolAddress returns for the current device, looked
+// up once per device (lbm_create) and kept in g_scratch_ptr.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)LBM_STATIC_SCRATCH_BYTES;
+__device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+lbm_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_check(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(LBM_E_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_check(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
 
 int q_of(int lat) { return lat; }
 
@@ -348,8 +381,12 @@ lbm_status lbm_create(const lbm_params* prm, void* ws, size_t bytes, void* strea
   if (((uintptr_t)ws & 255) != 0) return fail(LBM_E_INVAL, "workspace must be 256-byte aligned");
   if (bytes < L.total)
     return fail(LBM_E_NOMEM, "workspace has %zu bytes, needs %zu", bytes, L.total);
+  void* scr = nullptr;
+  s = scratch_of_current_device(&scr);
+  if (s != LBM_OK) return s;
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
   if (!c) return fail(LBM_E_NOMEM, "host allocation failed");
+  c->scratch = scr;
   c->prm = *prm;
   c->L = L;
   c->ns = (prm->flags & LBM_NS) != 0;
@@ -663,8 +700,10 @@ lbm_status backward_t(lbm_ctx* c, const void* gphi, const void* gT, int32_t gdt,
       for (int sd = 0; sd < 2; ++sd) {
         b.lTw[a][sd] = (Real*)p;
         p += align256(len * R);
-        hipError_t e = hipMemsetAsync(b.lTw[a][sd], 0, len * R, c->stream);
-        if (e != hipSuccess) return hip_check(e, "lbm_backward");
+        // accumulators start at zero (a fill kernel, not a memset node, so
+        // that a captured graph replays it correctly)
+        hipLaunchKernelGGL(k_fill, dim3((len + 255) / 256), dim3(256), 0, c->stream,
+                           (void*)b.lTw[a][sd], (long long)len, 0.0, sizeof(Real) == 8 ? 1 : 0);
       }
     }
   b.nc = node_const<Real>(c);
@@ -824,6 +863,21 @@ lbm_status lbm_backward(lbm_ctx* c, const void* g_phi, const void* g_T, const vo
                               out_dtype);
   return backward_t<float>(c, g_phi, g_T, seed_dtype, dev_ws, d_phi0, d_T0, d_Twall, tw_axis, tw_side,
                            out_dtype);
+}
+
+lbm_status lbm_backward_static(lbm_ctx* c, const void* g_phi, const void* g_T, const void* g_u,
+                               const void* g_p, int32_t seed_dtype, void* d_phi0, void* d_T0,
+                               void* d_Twall, int32_t tw_axis, int32_t tw_side, int32_t out_dtype) {
+  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  lbm_status st = adjoint_supported(c);
+  if (st != LBM_OK) return st;
+  const size_t need = adj_ws_bytes(c);
+  if (need > kScratchBytes)
+    return fail(LBM_E_NOMEM, "adjoint workspace of %zu bytes exceeds the static scratch of %zu bytes",
+                need, kScratchBytes);
+  if (!c->scratch) return fail(LBM_E_STATE, "no static scratch for this context");
+  return lbm_backward(c, g_phi, g_T, g_u, g_p, seed_dtype, c->scratch, kScratchBytes, d_phi0, d_T0,
+                      d_Twall, tw_axis, tw_side, out_dtype);
 }
 
 }  // extern "C"

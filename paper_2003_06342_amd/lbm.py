@@ -28,6 +28,7 @@ COLL = {"bgk": 0, "trt": 1, "mrt": 2}
 GRAD = {"central": 0, "biased1": 1, "biased2": 2}
 LBM_TAPE_SQRT, LBM_TAPE_BINOMIAL = 0, 1
 LBM_DT_F32, LBM_DT_F64 = 0, 1
+LBM_STATIC_SCRATCH_BYTES = 128 << 20   # include/lbm.h
 FIELDS = ["phi", "p", "ux", "uy", "uz", "T"]          # bit order of LBM_FIELD_*
 LAT = {"D2Q9": LBM_D2Q9, "D3Q7": LBM_D3Q7, "D3Q19": LBM_D3Q19}
 
@@ -89,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "lbm_forward_taped": (I32, [P, I64, I32, P, SZ]),
         "lbm_adjoint_workspace_size": (I32, [P, C.POINTER(SZ)]),
         "lbm_backward": (I32, [P, P, P, P, P, I32, P, SZ, P, P, P, I32, I32, I32]),
+        "lbm_backward_static": (I32, [P, P, P, P, P, I32, P, P, P, I32, I32, I32]),
         "lbm_destroy": (None, [P]),
         "lbm_last_error": (C.c_char_p, []),
         "lbm_version": (C.c_char_p, []),
@@ -303,6 +305,26 @@ class Sim:
                                      C.c_void_p(ptr), n, self._ptr(dphi), self._ptr(dT0),
                                      self._ptr(dTw), int(tw_face[0]), int(tw_face[1]), LBM_DT_F64))
         self._keep_ws = ws
+        return dict(phi0=dphi, T0=dT0, Tw=dTw)
+
+    def backward_static(self, gphi=None, tw_face=(1, 0), gT=None) -> dict:
+        """backward() through lbm_backward_static: no workspace argument (the
+        library's static device scratch); same seeds and outputs."""
+        torch = self.torch
+        shp = self.shape[1:]
+        g = None if gphi is None else self._dev(gphi, torch.float64).reshape(shp).contiguous()
+        gt = None if gT is None else self._dev(gT, torch.float64).reshape(shp).contiguous()
+        nx, ny = self.prm["nx"], self.prm["ny"]
+        dphi = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+        dT0 = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+        face_len = nx if tw_face[0] == 1 else ny
+        dTw = torch.empty(face_len, dtype=torch.float64, device=self.device)
+        none = C.c_void_p(None)
+        _check(self.lib.lbm_backward_static(self.ctx, self._ptr(g), self._ptr(gt), none, none,
+                                            LBM_DT_F64, self._ptr(dphi), self._ptr(dT0),
+                                            self._ptr(dTw), int(tw_face[0]), int(tw_face[1]),
+                                            LBM_DT_F64))
+        self._keep_seeds = (g, gt)
         return dict(phi0=dphi, T0=dT0, Tw=dTw)
 
     @property
