@@ -266,7 +266,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--only", choices=["film3d256", "adjoint", "film2d_f16dev", "film3d512_f32",
-                                       "film3d512_f16dev"],
+                                       "film3d512_f16dev", "multimode_f32", "multimode_f16dev"],
                     help="run one secondary measurement alone (for profiling) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -291,6 +291,13 @@ def main():
         f5 = I.film3d_fields(p5, seed=5, h0=64.0, amp=6.0)
         r = time_variant(p5, f5, st, args.steps, args.warmup)
         print(json.dumps({f"film3d_512^3_{st}": r}), flush=True)
+        return
+    if args.only in ("multimode_f32", "multimode_f16dev"):
+        st = args.only.split("_")[1]
+        pm = I.multimode_params(4096, 3072, jacob=0.1)
+        fm = I.multimode_fields(pm, seed=7)[:2]
+        r = time_variant(pm, fm, st, args.steps, args.warmup)
+        print(json.dumps({f"multimode_4096x3072_Ja0.1_{st}": r}), flush=True)
         return
     if args.only == "film2d_f16dev":
         p2 = I.film2d_params(1024, 2048)
@@ -340,6 +347,13 @@ def main():
                 var[name]["impl_hbm_frac"] = round(bi * rate, 4)
         for st in ("f64", "f16dev", "bf16dev"):
             record(f"film2d_1024x2048_{st}", prm, fields, st, 27, max(20, args.steps // 4), 5)
+        # second 2-D workload: the multi-mode film of Sec. 5.3 (4096 x 3072)
+        for ja in (0.1, 0.025):
+            pm = I.multimode_params(4096, 3072, jacob=ja)
+            fm = I.multimode_fields(pm, seed=7)[:2]
+            for st in (("f32", "f16dev") if ja == 0.1 else ("f32",)):
+                record(f"multimode_4096x3072_Ja{ja}_{st}", pm, fm, st, 27, max(20, args.steps // 4), 5)
+            del fm
         # the adjoint first: after the 3-D grids (tens of GB) it times slower
         try:
             var["adjoint_512x512_f32"] = adjoint_ratio()

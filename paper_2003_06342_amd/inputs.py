@@ -109,6 +109,57 @@ def film3d_params(n: int, wavelength: float | None = None, nz: int | None = None
     return p
 
 
+# Multi-mode film boiling (Sec. 5.3, the 4096 x 3072 run): the paper's
+# domain 5.12 x 3.84 at dx = 1.25e-3, the film-boiling set with gravity
+# such that the critical wavelength spans the same number of nodes as for
+# the lambda = 512 set (lambda_c = 512 * 0.2738 / 0.64 = 219 nodes, the
+# paper's 0.2738 / dx), and two Jacob numbers through L/Cp (T_w - T_sat = 1).
+MULTIMODE_LAMBDA_C = 512.0 / LAMBDA_OVER_LAMBDA_C
+
+
+def multimode_params(nx: int = 4096, ny: int = 3072, jacob: float = 0.1, **kw) -> dict:
+    """Multi-mode film: x periodic, walls at y = 0 and y = ny; Ja = Cp (T_w -
+    T_sat) / L, so L/Cp = 1 / Ja with T_w = 1 and T_sat = 0."""
+    p = film2d_params(nx, ny, wavelength=512.0)
+    p["L_over_cp"] = 1.0 / jacob
+    for k, v in kw.items():
+        p[k] = v
+    return p
+
+
+def multimode_modes(nx: int, seed: int, count: int = 16,
+                    lam_c: float = MULTIMODE_LAMBDA_C) -> np.ndarray:
+    """Wavelengths of the multi-mode initial interface: `count` values drawn
+    uniformly in [0.5 lambda_c, 1.5 sqrt(3) lambda_c] (Sec. 5.3), each
+    snapped to nx / k with k the nearest integer >= 1 so that every mode is
+    periodic on the x-periodic domain."""
+    rng = np.random.default_rng(seed)
+    lam = rng.uniform(0.5 * lam_c, 1.5 * math.sqrt(3.0) * lam_c, count)
+    k = np.maximum(1, np.rint(nx / lam))
+    return nx / k
+
+
+def multimode_fields(p: dict, seed: int = 7, y0: float = 24.0, y1: float = 0.75,
+                     count: int = 16):
+    """Vapour film h(x) = y0 + y1 sum_i sin(2 pi x / lambda_i) (Sec. 5.3) with
+    the modes of multimode_modes.  Defaults: y0 = 0.03 / dx = 24 nodes as in
+    the single-mode run, and y1 = (0.015 / dx) / 16 = 0.75 nodes, so that h
+    stays within the single-mode run's printed range [y0 - 12, y0 + 12]
+    nodes.  T = T_w (1 - y / h) below the film, T_sat above; u = 0, p = 0.
+    Returns (phi0, T0, modes)."""
+    nx, ny, W = p["nx"], p["ny"], p["W"]
+    lam = multimode_modes(nx, seed, count)
+    x = _centres(nx)
+    y = _centres(ny)
+    h = y0 + y1 * np.sin(2.0 * np.pi * x[None, :] / lam[:, None]).sum(axis=0)
+    H = h[None, :]
+    Y = y[:, None]
+    phi = tanh_profile(H - Y, W)
+    Tw, Tsat = p["T_wall"][1][0], p["T_sat"]
+    T = np.where(Y < H, Tsat + (Tw - Tsat) * (1.0 - Y / H), Tsat)
+    return phi[None].copy(), T[None].copy(), lam
+
+
 def drop_params(n: int = 128, **kw) -> dict:
     """Static drop, periodic box, heat off (Laplace-law set-up)."""
     p = base_params(dim=2, nx=n, ny=n, nz=1, heat=False, phase_change=False,
