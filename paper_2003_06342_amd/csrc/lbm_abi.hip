@@ -273,6 +273,9 @@ KArgs<Real, Store> make_args(const lbm_ctx* c) {
     for (int r = 0; r < 4; ++r) a.mrt[k][r] = (Real)p.mrt_rates[k][r];
   }
   a.grad_scheme = p.grad_scheme;
+  // non-temporal output stores once the two state buffers (populations and
+  // lagged planes) exceed the 256 MiB last-level cache (Infinity Cache)
+  a.nt = 2 * (c->L.pops + (size_t)c->L.nsc * c->L.scal) > ((size_t)256 << 20) ? 1 : 0;
   const int cur = c->cur;
   a.A = (const Store*)c->pops[cur];
   a.B = (Store*)c->pops[1 - cur];

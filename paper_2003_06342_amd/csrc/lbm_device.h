@@ -168,6 +168,7 @@ struct KArgs {
   Real lam[3];
   Real mrt[3][4];
   int grad_scheme;        // LBM_GRAD_*
+  int nt;                 // launch the non-temporal-store step kernel (state beyond the last-level cache)
   // macro output (MODE_MACRO): planes of nx*ny*nz
   void* out;
   int out_f64;
@@ -183,9 +184,27 @@ template <class T>
 __device__ __forceinline__ T ld_plane(const T* __restrict__ plane, unsigned idx) {
   return *(const T*)((const char*)plane + (size_t)(idx * (unsigned)sizeof(T)));
 }
-template <class T>
+// Store of the step's output: written once and not read again before the
+// next step.  NT (chosen per launch: the two state buffers exceed the 256 MiB
+// last-level cache): 4- and 8-byte values go out as non-temporal stores,
+// which keep them from displacing the halo pulls in L2 (FP32 steps: 1024 x
+// 2048 0.105 -> 0.100 ms, 4096 x 3072 0.611 -> 0.571 ms, 256^3 1.456 ->
+// 1.385 ms); on grids whose state stays in that cache they would send the
+// next step's reads to HBM (512 x 512 FP32 0.0138 -> 0.0173 ms).  16-bit
+// values use plain stores (non-temporal 2-byte stores made the FP16 1024 x
+// 2048 step 0.092 -> 0.099 ms).  Non-temporal loads of the s family (read
+// once) did not help.  A compile-time choice: a run-time branch between the
+// two stores is merged by the compiler into one plain store.
+template <bool NT, class T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+  if constexpr (NT && std::is_arithmetic<T>::value && sizeof(T) >= 4)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+template <bool NT = false, class T>
 __device__ __forceinline__ void st_plane(T* __restrict__ plane, unsigned idx, T v) {
-  *(T*)((char*)plane + (size_t)(idx * (unsigned)sizeof(T))) = v;
+  st_stream<NT>((T*)((char*)plane + (size_t)(idx * (unsigned)sizeof(T))), v);
 }
 
 // Element `idx` of a family block (all planes of one population family)
@@ -195,9 +214,9 @@ template <class T>
 __device__ __forceinline__ T ld_fam(const T* __restrict__ fam, unsigned idx) {
   return *(const T*)((const char*)fam + (size_t)(idx * (unsigned)sizeof(T)));
 }
-template <class T>
+template <bool NT, class T>
 __device__ __forceinline__ void st_fam(T* __restrict__ fam, unsigned idx, T v) {
-  *(T*)((char*)fam + (size_t)(idx * (unsigned)sizeof(T))) = v;
+  st_stream<NT>((T*)((char*)fam + (size_t)(idx * (unsigned)sizeof(T))), v);
 }
 
 __device__ inline int wrap1(int s, int n) {   // s in [-1, n]

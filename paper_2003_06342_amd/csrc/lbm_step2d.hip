@@ -33,7 +33,7 @@ struct StepTile {
   static constexpr int NT = TY <= 16 ? TX2 * TY : 512;
 };
 
-template <class Store, class Real, bool NS, bool HEAT, int MODE, bool FAST, int TY, bool EXT>
+template <class Store, class Real, bool NS, bool HEAT, int MODE, bool FAST, int TY, bool EXT, bool NTS>
 __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*sphi)[R1X],
                                             Real (*sux)[R2X], Real (*suy)[R2X], int x0, int y0) {
   using C = Codec<Real, Store>;
@@ -125,8 +125,8 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
           collide_s<D2Q9>(a, s, m, om);
         // 16-bit storage: the s deviations are about this node's own T
         const Real Tref = kNodeRef<Real, Store> ? (Real)(Sc)m.T : a.ref[2];
-        store_family<D2Q9>(a, a.off_s, 2, node, s, Tref);
-        if constexpr (kNodeRef<Real, Store>) st_plane(a.B_Tref, node, (Sc)m.T);
+        store_family<D2Q9, NTS>(a, a.off_s, 2, node, s, Tref);
+        if constexpr (kNodeRef<Real, Store>) st_plane<NTS>(a.B_Tref, node, (Sc)m.T);
       }
     }
     if constexpr (MODE == MODE_STEP) {
@@ -141,7 +141,7 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
         collide_g_ext<D2Q9>(a, g, m);
       else
         collide_g<D2Q9>(a, g, m);
-      store_family<D2Q9>(a, a.off_g, 1, node, g,
+      store_family<D2Q9, NTS>(a, a.off_g, 1, node, g,
                          kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1]);
     }
     const Real cs2 = (Real)(1.0 / 3.0);
@@ -166,12 +166,12 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
           collide_f_ext<D2Q9>(a, f, m, m.rho * cs2 * m.q * a.prod_fac, om, cproj);
         else
           collide_f<D2Q9>(f, m, m.rho * cs2 * m.q * a.prod_fac, om);
-        store_family<D2Q9>(a, a.off_f, 0, node, f, a.ref[0]);
+        store_family<D2Q9, NTS>(a, a.off_f, 0, node, f, a.ref[0]);
       }
     }
     if constexpr (MODE == MODE_STEP) {
-      st_plane(a.B_phip, node, (Sc)m.phi);
-      st_plane(a.B_qp, node, (Sc)m.q);
+      st_plane<NTS>(a.B_phip, node, (Sc)m.phi);
+      st_plane<NTS>(a.B_qp, node, (Sc)m.q);
     } else {
       const long long plane = (long long)a.nx * a.ny * a.nz;
       const long long idx = (long long)y * a.nx + x;
@@ -204,7 +204,7 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
   }
 }
 
-template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT>
+template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT, bool NTS>
 __device__ __forceinline__ void step2d_body(const KArgs<Real, Store>& a) {
   __shared__ Real sphi[Tile2<TY>::R1Y][R1X];
   __shared__ Real sux[Tile2<TY>::R2Y][R2X];
@@ -221,26 +221,26 @@ __device__ __forceinline__ void step2d_body(const KArgs<Real, Store>& a) {
   // lies inside the domain, so no wall link and no periodic wrap occurs
   const bool interior = x0 >= 3 && x0 + TX2 + 3 <= a.nx && y0 >= 3 && y0 + TY + 3 <= a.ny;
   if (interior)
-    step_tile2d<Store, Real, NS, HEAT, MODE, true, TY, EXT>(a, sphi, sux, suy, x0, y0);
+    step_tile2d<Store, Real, NS, HEAT, MODE, true, TY, EXT, NTS>(a, sphi, sux, suy, x0, y0);
   else
-    step_tile2d<Store, Real, NS, HEAT, MODE, false, TY, EXT>(a, sphi, sux, suy, x0, y0);
+    step_tile2d<Store, Real, NS, HEAT, MODE, false, TY, EXT, NTS>(a, sphi, sux, suy, x0, y0);
 }
 
 // EXT: the extended step (TRT / MRT collision, biased directional
 // derivatives, local div(u phi)), selected at run time from the arguments;
 // the default kernels are BGK with central derivatives.
-template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT>
+template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT, bool NTS>
 __global__ __launch_bounds__(StepTile<TY>::NT) void k_step2d(const KArgs<Real, Store> a) {
-  step2d_body<Store, Real, NS, HEAT, MODE, TY, EXT>(a);
+  step2d_body<Store, Real, NS, HEAT, MODE, TY, EXT, NTS>(a);
 }
 
 // 16-bit storage: at most 128 VGPRs (4 waves per SIMD).  The codec constants
 // and per-node references pushed the 64-row tile kernel past that (0.200 ->
 // 0.136 ms at 1024 x 2048 with the cap); the 4-row carry kernel needs 72.
-template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT>
+template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT, bool NTS>
 __global__ __launch_bounds__(StepTile<TY>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_step2d_w4(
     const KArgs<Real, Store> a) {
-  step2d_body<Store, Real, NS, HEAT, MODE, TY, EXT>(a);
+  step2d_body<Store, Real, NS, HEAT, MODE, TY, EXT, NTS>(a);
 }
 
 // Initialisation: populations = equilibrium - S/2 at the given fields with
@@ -441,19 +441,22 @@ static hipError_t launch_step2d_t(const KArgs<Real, Store>& a, int ns, int heat,
   const int ty = mode != MODE_STEP ? 64 : (small_tiles ? 4 : 16);
   const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + ty - 1) / ty);
   const bool ext = a.coll != COLL_BGK || a.grad_scheme != GRAD_CENTRAL || a.div_local;
-#define LBM_K(NSV, HV, MV, TYV, EV)                                                             \
+#define LBM_K(NSV, HV, MV, TYV, EV, NTV)                                                        \
   do {                                                                                          \
     if constexpr (st16)                                                                         \
-      hipLaunchKernelGGL((k_step2d_w4<Store, Real, NSV, HV, MV, TYV, EV>), dim3(tiles),        \
+      hipLaunchKernelGGL((k_step2d_w4<Store, Real, NSV, HV, MV, TYV, EV, NTV>), dim3(tiles),   \
                          dim3(StepTile<TYV>::NT), 0, st, a);                                    \
     else                                                                                        \
-      hipLaunchKernelGGL((k_step2d<Store, Real, NSV, HV, MV, TYV, EV>), dim3(tiles),           \
+      hipLaunchKernelGGL((k_step2d<Store, Real, NSV, HV, MV, TYV, EV, NTV>), dim3(tiles),      \
                          dim3(StepTile<TYV>::NT), 0, st, a);                                    \
   } while (0)
-#define LBM_L(NSV, HV, MV, TYV)                      \
-  do {                                               \
-    if (ext) LBM_K(NSV, HV, MV, TYV, true);          \
-    else LBM_K(NSV, HV, MV, TYV, false);             \
+// the default step with or without non-temporal stores; the extended step
+// with plain stores
+#define LBM_L(NSV, HV, MV, TYV)                         \
+  do {                                                  \
+    if (ext) LBM_K(NSV, HV, MV, TYV, true, false);      \
+    else if (a.nt) LBM_K(NSV, HV, MV, TYV, false, true); \
+    else LBM_K(NSV, HV, MV, TYV, false, false);         \
   } while (0)
 #define LBM_L2(NSV, HV, MV)                \
   if constexpr (small_tiles) LBM_L(NSV, HV, MV, 4); \
@@ -465,10 +468,10 @@ static hipError_t launch_step2d_t(const KArgs<Real, Store>& a, int ns, int heat,
     else { LBM_L2(false, false, MODE_STEP); }
   } else {
     // the fields pass takes the local div(u phi) at run time
-    if (ns && heat) LBM_K(true, true, MODE_MACRO, 64, false);
-    else if (ns) LBM_K(true, false, MODE_MACRO, 64, false);
-    else if (heat) LBM_K(false, true, MODE_MACRO, 64, false);
-    else LBM_K(false, false, MODE_MACRO, 64, false);
+    if (ns && heat) LBM_K(true, true, MODE_MACRO, 64, false, false);
+    else if (ns) LBM_K(true, false, MODE_MACRO, 64, false, false);
+    else if (heat) LBM_K(false, true, MODE_MACRO, 64, false, false);
+    else LBM_K(false, false, MODE_MACRO, 64, false, false);
   }
 #undef LBM_L2
 #undef LBM_L

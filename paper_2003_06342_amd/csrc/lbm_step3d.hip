@@ -87,14 +87,14 @@ __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z
   }
 }
 
-template <class Lat, class Real, class Store>
+template <class Lat, bool NT = false, class Real, class Store>
 __device__ inline void store3d(const KArgs<Real, Store>& a, int off, int fam, unsigned node,
                                const Real* v, Real ref) {
   using C = Codec<Real, Store>;
   Store* __restrict__ base = a.B + (size_t)off * (size_t)a.slab;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i)
-    (base + (size_t)i * (size_t)a.slab)[node] = C::enc(v[i], (Real)Lat::w(i) * ref, a.scale[fam]);
+    st_stream<NT>(&(base + (size_t)i * (size_t)a.slab)[node], C::enc(v[i], (Real)Lat::w(i) * ref, a.scale[fam]));
 }
 
 // D3Q19 directional-derivative gradient and Laplacian from the phi ring
@@ -159,7 +159,7 @@ __device__ inline int zplane(int p, int nz, int wall, bool& ghost) {
   return wrapmod(p, nz);
 }
 
-template <class S, class Store, class Real, bool NS, bool HEAT, int MODE, bool XYIN, bool EXT>
+template <class S, class Store, class Real, bool NS, bool HEAT, int MODE, bool XYIN, bool EXT, bool NTS>
 __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi)[S::P1Y][S::P1X],
                                         Real (*su)[3][S::P2Y][S::P2X], int x0, int y0, int z0, int z1) {
   using Sc = typename ScalarOf<Store>::T;
@@ -302,8 +302,8 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
           else
             collide_s<D3Q7>(a, s, m, om);
           const Real Tref = kNodeRef<Real, Store> ? (Real)(Sc)m.T : a.ref[2];
-          store3d<D3Q7>(a, a.off_s, 2, node, s, Tref);
-          if constexpr (kNodeRef<Real, Store>) a.B_Tref[node] = (Sc)m.T;
+          store3d<D3Q7, NTS>(a, a.off_s, 2, node, s, Tref);
+          if constexpr (kNodeRef<Real, Store>) st_stream<NTS>(&a.B_Tref[node], (Sc)m.T);
         }
       }
       if constexpr (MODE == MODE_STEP) {
@@ -313,7 +313,7 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
           collide_g_ext<D3Q7>(a, g, m);
         else
           collide_g<D3Q7>(a, g, m);
-        store3d<D3Q7>(a, a.off_g, 1, node, g, kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1]);
+        store3d<D3Q7, NTS>(a, a.off_g, 1, node, g, kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1]);
       }
       const Real cs2 = (Real)(1.0 / 3.0);
       m.p = 0;
@@ -334,12 +334,12 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
             });
           else
             collide_f<D3Q19>(f, m, m.rho * cs2 * m.q * a.prod_fac, om);
-          store3d<D3Q19>(a, a.off_f, 0, node, f, a.ref[0]);
+          store3d<D3Q19, NTS>(a, a.off_f, 0, node, f, a.ref[0]);
         }
       }
       if constexpr (MODE == MODE_STEP) {
-        a.B_phip[node] = (Sc)m.phi;
-        a.B_qp[node] = (Sc)m.q;
+        st_stream<NTS>(&a.B_phip[node], (Sc)m.phi);
+        st_stream<NTS>(&a.B_qp[node], (Sc)m.q);
       } else {
         const long long plane = (long long)a.nx * a.ny * a.nz;
         const long long idx = ((long long)z * a.ny + y) * a.nx + x;
@@ -392,7 +392,7 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
 
 // EXT: the extended step (TRT / MRT collision, biased directional
 // derivatives, local div(u phi)), selected at run time from the arguments.
-template <class S, class Store, class Real, bool NS, bool HEAT, int MODE, bool EXT>
+template <class S, class Store, class Real, bool NS, bool HEAT, int MODE, bool EXT, bool NTS>
 __global__ __launch_bounds__(S::NT) void k_step3d(const KArgs<Real, Store> a) {
   __shared__ Real sphi[NPHI][S::P1Y][S::P1X];
   __shared__ Real su[NU][3][S::P2Y][S::P2X];
@@ -407,9 +407,9 @@ __global__ __launch_bounds__(S::NT) void k_step3d(const KArgs<Real, Store> a) {
   const int z1 = min(z0 + S::ZC, a.nz);
   const bool xyin = x0 >= 3 && x0 + S::TX + 3 <= a.nx && y0 >= 3 && y0 + S::TY + 3 <= a.ny;
   if (xyin)
-    march3d<S, Store, Real, NS, HEAT, MODE, true, EXT>(a, sphi, su, x0, y0, z0, z1);
+    march3d<S, Store, Real, NS, HEAT, MODE, true, EXT, NTS>(a, sphi, su, x0, y0, z0, z1);
   else
-    march3d<S, Store, Real, NS, HEAT, MODE, false, EXT>(a, sphi, su, x0, y0, z0, z1);
+    march3d<S, Store, Real, NS, HEAT, MODE, false, EXT, NTS>(a, sphi, su, x0, y0, z0, z1);
 }
 
 // Initialisation (3-D): equilibrium - S/2 at the initial fields, scattered
@@ -588,25 +588,28 @@ static hipError_t launch_step3d_t(const KArgs<Real, Store>& a, int ns, int heat,
   // the FP32 step on the wide shape; everything else (and the fields pass,
   // whose per-block partials are sized by step3d_blocks) on the standard one
   const bool ext = a.coll != COLL_BGK || a.grad_scheme != GRAD_CENTRAL || a.div_local;
-  const bool wide = mode == MODE_STEP && !ext && std::is_same<Store, float>::value;
-#define LBM_L(NSV, HV, MV)                                                                     \
-  do {                                                                                         \
-    if constexpr (MV == MODE_STEP) {                                                           \
-      if (ext) {                                                                               \
-        hipLaunchKernelGGL((k_step3d<ShapeStd3, Store, Real, NSV, HV, MV, true>),             \
-                           dim3(blocks3d<ShapeStd3>(a.nx, a.ny, a.nz)), dim3(ShapeStd3::NT), 0, \
-                           st, a);                                                             \
-        break;                                                                                 \
-      }                                                                                        \
-    }                                                                                          \
-    if (wide)                                                                                  \
-      hipLaunchKernelGGL((k_step3d<ShapeWide3, Store, Real, NSV, HV, MV, false>),             \
-                         dim3(blocks3d<ShapeWide3>(a.nx, a.ny, a.nz)), dim3(ShapeWide3::NT), 0, \
-                         st, a);                                                               \
-    else                                                                                       \
-      hipLaunchKernelGGL((k_step3d<ShapeStd3, Store, Real, NSV, HV, MV, false>),              \
-                         dim3(blocks3d<ShapeStd3>(a.nx, a.ny, a.nz)), dim3(ShapeStd3::NT), 0,   \
-                         st, a);                                                               \
+  constexpr bool kWide = std::is_same<Store, float>::value;
+#define LBM_K(SH, NSV, HV, MV, EV, NTV)                                                        \
+  hipLaunchKernelGGL((k_step3d<SH, Store, Real, NSV, HV, MV, EV, NTV>),                         \
+                     dim3(blocks3d<SH>(a.nx, a.ny, a.nz)), dim3(SH::NT), 0, st, a)
+// the step: extended (standard shape, plain stores), or the default on the
+// wide (FP32) or standard shape with or without non-temporal stores; the
+// fields pass on the standard shape
+#define LBM_L(NSV, HV, MV)                                                                   \
+  do {                                                                                       \
+    if constexpr (MV == MODE_STEP) {                                                         \
+      if (ext) {                                                                             \
+        LBM_K(ShapeStd3, NSV, HV, MV, true, false);                                          \
+      } else if constexpr (kWide) {                                                          \
+        if (a.nt) LBM_K(ShapeWide3, NSV, HV, MV, false, true);                               \
+        else LBM_K(ShapeWide3, NSV, HV, MV, false, false);                                   \
+      } else {                                                                               \
+        if (a.nt) LBM_K(ShapeStd3, NSV, HV, MV, false, true);                                \
+        else LBM_K(ShapeStd3, NSV, HV, MV, false, false);                                    \
+      }                                                                                      \
+    } else {                                                                                 \
+      LBM_K(ShapeStd3, NSV, HV, MV, false, false);                                           \
+    }                                                                                        \
   } while (0)
   if (mode == MODE_STEP) {
     if (ns && heat) LBM_L(true, true, MODE_STEP);
@@ -620,6 +623,7 @@ static hipError_t launch_step3d_t(const KArgs<Real, Store>& a, int ns, int heat,
     else LBM_L(false, false, MODE_MACRO);
   }
 #undef LBM_L
+#undef LBM_K
   return hipGetLastError();
 }
 

@@ -84,15 +84,15 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
 // Store the Q post-collision populations of one family at `node` of B.
 // ref: the deviation reference (the family's global one, or the node's
 // T_ref for the s family in 16-bit storage).
-template <class Lat, class Real, class Store>
+template <class Lat, bool NT = false, class Real, class Store>
 __device__ inline void store_family(const KArgs<Real, Store>& a, int off, int fam, unsigned node,
                                     const Real* v, Real ref) {
   using C = Codec<Real, Store>;
   Store* __restrict__ base = a.B + (size_t)off * (size_t)a.slab;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i)
-    st_fam(base, (unsigned)i * (unsigned)a.slab + node,
-           C::enc(v[i], (Real)Lat::w(i) * ref, a.scale[fam]));
+    st_fam<NT>(base, (unsigned)i * (unsigned)a.slab + node,
+               C::enc(v[i], (Real)Lat::w(i) * ref, a.scale[fam]));
 }
 
 // Directional-derivative gradient and Laplacian (Eqs. DerivDirec_Grad, Grad,

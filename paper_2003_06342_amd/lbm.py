@@ -71,6 +71,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} not built; run __graft_entry__.build() first")
+    # torch ships its own HIP runtime; importing it first makes the library
+    # bind to that same runtime (whose memory and streams it is given)
+    # instead of loading a second one, which then sees no device
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P, I32, I64, SZ, U32, D = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.c_uint32, C.c_double
     sig = {
