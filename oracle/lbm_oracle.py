@@ -67,6 +67,13 @@ same ones):
       BGK rate (pxx, pxy for f; j for g and s), the others at the free rates
       (s_e for rho and e, s_eps, s_q for q (and j of f), s_p for the
       second-order moments of g and s).
+  R29 an open face of f (flag per face): the pressure anti-bounce-back
+      f_i = -f*_{i'} + 2 w_i p_w, the even part of Eq. Feq_NS_Incompr at the
+      face pressure with its O(u^2) terms dropped (Ginzburg's rule for a
+      Dirichlet condition on the zeroth moment), and a stencil ghost
+      u_g = u_b (zero normal gradient) instead of the no-slip -u_b.  g and s
+      keep their Dirichlet anti-bounce-back.  Lets net evaporation leave a
+      closed box, whose gauge pressure otherwise drifts.
   R27 biased directional derivatives (Sec. 3.4, after Eq. Laplacian: the
       first- and second-order upwind differences phi(x + c) - phi(x) and
       [-phi(x + 2c) + 4 phi(x + c) - 3 phi(x)] / 2, offered there as
@@ -247,6 +254,11 @@ class Model:
         self.H = 12.0 * self.sigma / self.W
         self.wall = [prm["bc"][a] == "wall" for a in range(3)]
         self.phi_w = [[float(prm["phi_wall"][a][s]) for s in range(2)] for a in range(3)]
+        # open faces of f (R29): pressure anti-bounce-back instead of no-slip
+        fo = prm.get("f_open", [[False, False]] * 3)
+        pw = prm.get("p_wall", [[0.0, 0.0]] * 3)
+        self.f_open = [[bool(fo[a][s]) and self.wall[a] for s in range(2)] for a in range(3)]
+        self.p_w = [[float(pw[a][s]) for s in range(2)] for a in range(3)]
         self.T_w = [[torch.tensor(float(prm["T_wall"][a][s]), dtype=self.dt)
                      for s in range(2)] for a in range(3)]
         if T_wall_faces:
@@ -289,7 +301,9 @@ class Model:
                 lo = 2.0 * self.phi_w[a][0] - first
                 hi = 2.0 * self.phi_w[a][1] - last
             elif kind == "anti":
-                lo, hi = -first, -last
+                # no-slip: u_g = -u_b; an open face (R29): u_g = u_b
+                lo = first if self.f_open[a][0] else -first
+                hi = last if self.f_open[a][1] else -last
             else:
                 raise ValueError(kind)
             out = torch.cat([lo, out, hi], dim=d)
@@ -614,8 +628,9 @@ class Model:
 
     def stream(self, post, L: Lattice, kind: str, wall_val=None):
         """Pull streaming new_i(x) = post_i(x - c_i) (periodic roll); at a wall
-        the link reflects: bounce-back new_i = post_{i'} ('bb') or
-        anti-bounce-back new_i = -post_{i'} + 2 w_i V_w ('abb', Sec. 3.3)."""
+        the link reflects: bounce-back new_i = post_{i'} ('bb', an open face of
+        f instead -post_{i'} + 2 w_i p_w, R29) or anti-bounce-back
+        new_i = -post_{i'} + 2 w_i V_w ('abb', Sec. 3.3)."""
         out = []
         for i in range(L.Q):
             c = L.c[i]
@@ -626,7 +641,8 @@ class Model:
                 side = 0 if c[a] > 0 else 1
                 mask = self._boundary_mask(a, side)
                 if kind == "bb":
-                    repl = post[L.opp[i]]
+                    repl = (-post[L.opp[i]] + 2.0 * L.w[i] * self.p_w[a][side]
+                            if self.f_open[a][side] else post[L.opp[i]])
                 else:
                     repl = -post[L.opp[i]] + 2.0 * L.w[i] * wall_val[a][side]
                 v = torch.where(mask, repl, v)

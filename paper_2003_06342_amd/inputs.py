@@ -45,6 +45,8 @@ _BASE = dict(
     bc=["periodic", "periodic", "periodic"],
     phi_wall=[[0.0, 0.0], [0.0, 0.0], [0.0, 0.0]],
     T_wall=[[0.0, 0.0], [0.0, 0.0], [0.0, 0.0]],
+    f_open=[[False, False], [False, False], [False, False]],   # open (pressure) faces of f
+    p_wall=[[0.0, 0.0], [0.0, 0.0], [0.0, 0.0]],               # their pressure
     eps_n=1e-3,
     div_local=False,
     collision="bgk",                  # "bgk" | "trt" | "mrt"
