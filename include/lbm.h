@@ -149,7 +149,18 @@ typedef struct {
                                   * values every check_every steps (FP64
                                   * reduction; synchronises) and returns
                                   * LBM_E_UNSTABLE at the first failure     */
+  /* Per wall face [axis][lo, hi], the condition of f: LBM_FBC_NOSLIP
+   * (half-way bounce-back, Sec. 4.1.2) or LBM_FBC_PRESSURE, an open face at
+   * pressure p_wall: the pressure anti-bounce-back f_i = -f_{i'} + 2 w_i
+   * p_wall (the even part of Eq. Feq_NS_Incompr at the face pressure, its
+   * O(u^2) terms dropped) with a zero-gradient velocity ghost for the
+   * stencils.  g and s keep their Dirichlet anti-bounce-back.  Lets the
+   * vapour produced by evaporation leave a closed box, whose gauge pressure
+   * otherwise drifts.  Only on walled axes (LBM_E_INVAL otherwise). */
+  int32_t f_bc[3][2];
+  double p_wall[3][2];
 } lbm_params;
+enum { LBM_FBC_NOSLIP = 0, LBM_FBC_PRESSURE = 1 };
 /* Kernels: BGK with central derivatives and the radius-2 div(u phi) runs the
  * default step kernels; any of TRT / MRT, a biased scheme or LBM_DIV_LOCAL
  * (which needs LBM_NS | LBM_HEAT) runs the extended step kernels, with the

@@ -171,6 +171,15 @@ lbm_status validate(const lbm_params* p) {
   if ((p->flags & LBM_DIV_LOCAL) && !((p->flags & LBM_NS) && (p->flags & LBM_HEAT)))
     return fail(LBM_E_INVAL, "LBM_DIV_LOCAL needs LBM_NS and LBM_HEAT");
   if (p->check_every < 0) return fail(LBM_E_INVAL, "check_every must be >= 0");
+  for (int a = 0; a < 3; ++a)
+    for (int sd = 0; sd < 2; ++sd) {
+      const int fb = p->f_bc[a][sd];
+      if (fb != LBM_FBC_NOSLIP && fb != LBM_FBC_PRESSURE)
+        return fail(LBM_E_INVAL, "unknown f_bc[%d][%d] = %d", a, sd, fb);
+      if (fb == LBM_FBC_PRESSURE && p->bc[a] != LBM_BC_WALL)
+        return fail(LBM_E_INVAL, "f_bc[%d][%d]: an open face needs a walled axis", a, sd);
+      if (!std::isfinite(p->p_wall[a][sd])) return fail(LBM_E_INVAL, "p_wall must be finite");
+    }
   if (p->dim == 2) {
     // the 2-D kernel addresses each population family with 32-bit byte offsets
     const long long px = (p->nx + 63) / 64 * 64;
@@ -232,6 +241,8 @@ KArgs<Real, Store> make_args(const lbm_ctx* c) {
     for (int s = 0; s < 2; ++s) {
       a.Tw[d][s] = (const Real*)c->tw[d][s];
       a.phi_w[d][s] = (Real)p.phi_wall[d][s];
+      a.f_open[d][s] = p.f_bc[d][s] == LBM_FBC_PRESSURE ? 1 : 0;
+      a.p_w[d][s] = (Real)p.p_wall[d][s];
     }
   for (int k = 0; k < 3; ++k) {
     a.ref[k] = (Real)c->ref[k];
@@ -641,6 +652,10 @@ lbm_status adjoint_supported(const lbm_ctx* c) {
   if (p.grad_scheme != LBM_GRAD_CENTRAL)
     return fail(LBM_E_UNSUPPORTED, "adjoint is built for central gradients");
   if (p.flags & LBM_DIV_LOCAL) return fail(LBM_E_UNSUPPORTED, "adjoint is built without LBM_DIV_LOCAL");
+  for (int a = 0; a < 3; ++a)
+    for (int sd = 0; sd < 2; ++sd)
+      if (p.f_bc[a][sd] != LBM_FBC_NOSLIP)
+        return fail(LBM_E_UNSUPPORTED, "adjoint is built for no-slip faces of f");
   return LBM_OK;
 }
 

@@ -153,6 +153,9 @@ struct KArgs {
   // per-node wall temperature on each walled face: [axis][side]
   const Real* __restrict__ Tw[3][2];
   Real phi_w[3][2];
+  // open (pressure) faces of f: pressure anti-bounce-back at p_w
+  int f_open[3][2];
+  Real p_w[3][2];
   // codec constants per family (f, g, s)
   Real ref[3], scale[3], inv_scale[3];
   // physics

@@ -275,15 +275,16 @@ __global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, cons
     }
     return add + sgn * v;
   };
+  // u ghost: -u_b beyond a no-slip face, u_b beyond an open face of f
   auto u_at = [&](int comp, int xx, int yy) -> Real {
     if (!u0) return 0;
     Real sgn = 1;
     if (a.wall[1] && (yy < 0 || yy >= a.ny)) {
-      sgn = -sgn;
+      if (!a.f_open[1][yy < 0 ? 0 : 1]) sgn = -sgn;
       yy = mirror(yy, a.ny);
     } else if (!a.wall[1]) yy = wrap1(yy, a.ny);
     if (a.wall[0] && (xx < 0 || xx >= a.nx)) {
-      sgn = -sgn;
+      if (!a.f_open[0][xx < 0 ? 0 : 1]) sgn = -sgn;
       xx = mirror(xx, a.nx);
     } else if (!a.wall[0]) xx = wrap1(xx, a.nx);
     return sgn * ld(u0, comp, xx, yy);
@@ -383,16 +384,16 @@ __global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, cons
       const int j = D2Q9::opp(i);
       const long long node = (long long)y * a.px + x;
       Real Vg, Vs;
-      if (oy) {
-        const int side = sy < 0 ? 0 : 1;
-        Vg = a.phi_w[1][side];
-        Vs = HEAT ? a.Tw[1][side][x] : (Real)0;
-      } else {
-        const int side = sx < 0 ? 0 : 1;
-        Vg = a.phi_w[0][side];
-        Vs = HEAT ? a.Tw[0][side][y] : (Real)0;
-      }
-      if (NS) a.B[(long long)(a.off_f + j) * a.slab + node] = C::enc(f[i], w * a.ref[0], a.scale[0]);
+      const int ax = oy ? 1 : 0;
+      const int side = oy ? (sy < 0 ? 0 : 1) : (sx < 0 ? 0 : 1);
+      Vg = a.phi_w[ax][side];
+      Vs = HEAT ? (oy ? a.Tw[1][side][x] : a.Tw[0][side][y]) : (Real)0;
+      // bounce-back returns the slot as is; an open face returns
+      // -slot + 2 w_i p_w, so its slot holds 2 w_i p_w - f_i
+      if (NS)
+        a.B[(long long)(a.off_f + j) * a.slab + node] =
+            C::enc(a.f_open[ax][side] ? (Real)2 * w * a.p_w[ax][side] - f[i] : f[i], w * a.ref[0],
+                   a.scale[0]);
       const Real gr = kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1];   // slot at this node
       a.B[(long long)(a.off_g + j) * a.slab + node] =
           C::enc((Real)2 * w * Vg - g[i], w * gr, a.scale[1]);

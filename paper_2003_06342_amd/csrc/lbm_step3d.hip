@@ -62,10 +62,12 @@ __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z
       const int j = Lat::opp(i);
       const Real wr = NREF ? (Real)Lat::w(i) * (Real)rplane[node] : wref;
       Real r = C::dec((base + (size_t)j * (size_t)a.slab)[node], wr, inv);
+      const int side = sz < 0 ? 0 : 1;
       if (FAM != 0) {
-        const int side = sz < 0 ? 0 : 1;
         const Real V = FAM == 1 ? a.phi_w[2][side] : a.Tw[2][side][y * a.nx + x];
         r = -r + (Real)2 * (Real)Lat::w(i) * V;
+      } else if (a.f_open[2][side]) {   // open face: pressure anti-bounce-back
+        r = -r + (Real)2 * (Real)Lat::w(i) * a.p_w[2][side];
       }
       v[i] = r;
     } else {
@@ -217,7 +219,8 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const Real u = ((Real)3 * m[d] + (Real)0.5 * F[d]) * ir;
-        su[s][d][ry][rx] = ghost ? -u : u;
+        // ghost plane: -u beyond a no-slip face, u beyond an open one
+        su[s][d][ry][rx] = (ghost && !a.f_open[2][p < 0 ? 0 : 1]) ? -u : u;
       }
     }
   };
@@ -439,7 +442,10 @@ __global__ __launch_bounds__(256) void k_init3d(const KArgs<Real, Store> a, cons
     if (!u0) return 0;
     xx = wrap1(xx, a.nx);
     yy = wrap1(yy, a.ny);
-    if (a.wall[2] && (zz < 0 || zz >= a.nz)) return -ld(u0, c, xx, yy, mirror3(zz, a.nz));
+    if (a.wall[2] && (zz < 0 || zz >= a.nz)) {
+      const Real ub = ld(u0, c, xx, yy, mirror3(zz, a.nz));
+      return a.f_open[2][zz < 0 ? 0 : 1] ? ub : -ub;
+    }
     if (!a.wall[2]) zz = wrap1(zz, a.nz);
     return ld(u0, c, xx, yy, zz);
   };
@@ -524,7 +530,10 @@ __global__ __launch_bounds__(256) void k_init3d(const KArgs<Real, Store> a, cons
       const int sz = z - D3Q19::cz(i);
       if (a.wall[2] && (sz < 0 || sz >= a.nz)) {
         const unsigned node = (unsigned)(z * pz + y * a.px + x);
-        a.B[(size_t)(a.off_f + D3Q19::opp(i)) * a.slab + node] = C::enc(val, w * a.ref[0], a.scale[0]);
+        // an open face returns -slot + 2 w_i p_w: its slot holds 2 w_i p_w - f_i
+        const int side = sz < 0 ? 0 : 1;
+        const Real sv = a.f_open[2][side] ? (Real)2 * w * a.p_w[2][side] - val : val;
+        a.B[(size_t)(a.off_f + D3Q19::opp(i)) * a.slab + node] = C::enc(sv, w * a.ref[0], a.scale[0]);
       } else {
         const int sx = wrap1(x - D3Q19::cx(i), a.nx), sy = wrap1(y - D3Q19::cy(i), a.ny);
         const int szz = a.wall[2] ? sz : wrap1(sz, a.nz);

@@ -59,16 +59,13 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
       const int j = Lat::opp(i);
       const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, node) : wref;
       Real r = C::dec(ld_fam(base, (unsigned)j * (unsigned)a.slab + node), wr, inv);
+      const int ax = oy ? 1 : 0;
+      const int side = oy ? (sy < 0 ? 0 : 1) : (sx < 0 ? 0 : 1);
       if (FAM != 0) {
-        Real V;
-        if (oy) {
-          const int side = sy < 0 ? 0 : 1;
-          V = FAM == 1 ? a.phi_w[1][side] : a.Tw[1][side][x];
-        } else {
-          const int side = sx < 0 ? 0 : 1;
-          V = FAM == 1 ? a.phi_w[0][side] : a.Tw[0][side][y];
-        }
+        const Real V = FAM == 1 ? a.phi_w[ax][side] : (oy ? a.Tw[1][side][x] : a.Tw[0][side][y]);
         r = -r + (Real)2 * (Real)Lat::w(i) * V;
+      } else if (a.f_open[ax][side]) {   // open face: pressure anti-bounce-back
+        r = -r + (Real)2 * (Real)Lat::w(i) * a.p_w[ax][side];
       }
       v[i] = r;
     } else {
@@ -306,9 +303,11 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
         const int gx = x0 - 1 + rx;
         if (gx < 0 || gx >= a.nx) {
           const int mx = mirror(gx, a.nx) - (x0 - 1);
+          // no-slip ghost -u_b; open face u_b (zero normal gradient)
+          const Real sg = a.f_open[0][gx < 0 ? 0 : 1] ? (Real)1 : (Real)-1;
           if (mx >= 0 && mx < R2X) {
-            sux[ry][rx] = -sux[ry][mx];
-            suy[ry][rx] = -suy[ry][mx];
+            sux[ry][rx] = sg * sux[ry][mx];
+            suy[ry][rx] = sg * suy[ry][mx];
           }
         }
       }
@@ -320,9 +319,10 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
         const int gy = y0 - 1 + ry;
         if (gy < 0 || gy >= a.ny) {
           const int my = mirror(gy, a.ny) - (y0 - 1);
+          const Real sg = a.f_open[1][gy < 0 ? 0 : 1] ? (Real)1 : (Real)-1;
           if (my >= 0 && my < Tile2<TY>::R2Y) {
-            sux[ry][rx] = -sux[my][rx];
-            suy[ry][rx] = -suy[my][rx];
+            sux[ry][rx] = sg * sux[my][rx];
+            suy[ry][rx] = sg * suy[my][rx];
           }
         }
       }

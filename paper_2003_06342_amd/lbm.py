@@ -28,6 +28,7 @@ COLL = {"bgk": 0, "trt": 1, "mrt": 2}
 GRAD = {"central": 0, "biased1": 1, "biased2": 2}
 LBM_TAPE_SQRT, LBM_TAPE_BINOMIAL = 0, 1
 LBM_DT_F32, LBM_DT_F64 = 0, 1
+LBM_FBC_NOSLIP, LBM_FBC_PRESSURE = 0, 1
 LBM_STATIC_SCRATCH_BYTES = 128 << 20   # include/lbm.h
 FIELDS = ["phi", "p", "ux", "uy", "uz", "T"]          # bit order of LBM_FIELD_*
 LAT = {"D2Q9": LBM_D2Q9, "D3Q7": LBM_D3Q7, "D3Q19": LBM_D3Q19}
@@ -58,6 +59,8 @@ class lbm_params(C.Structure):
         ("mrt_rates", (C.c_double * 4) * 3),
         ("grad_scheme", C.c_int32),
         ("check_every", C.c_int32),
+        ("f_bc", (C.c_int32 * 2) * 3),
+        ("p_wall", (C.c_double * 2) * 3),
     ]
 
 
@@ -135,6 +138,12 @@ def make_params(prm: dict, storage: str) -> lbm_params:
             p.mrt_rates[k][r] = float(rates[k][r])
     p.grad_scheme = GRAD[prm.get("grad_scheme", "central")]
     p.check_every = int(prm.get("check_every", 0))
+    f_open = prm.get("f_open", [[False, False]] * 3)
+    p_wall = prm.get("p_wall", [[0.0, 0.0]] * 3)
+    for a in range(3):
+        for s in range(2):
+            p.f_bc[a][s] = LBM_FBC_PRESSURE if f_open[a][s] else LBM_FBC_NOSLIP
+            p.p_wall[a][s] = float(p_wall[a][s])
     for k in ("nu_l", "nu_g", "mobility", "alpha_l", "alpha_g", "W", "sigma", "rho_l", "rho_g",
               "L_over_cp", "T_sat", "theta_I", "A_coef", "eps_n"):
         setattr(p, k, float(prm[k]))

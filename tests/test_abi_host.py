@@ -154,6 +154,25 @@ def test_extended_options_validated(lib):
     assert lib.lbm_workspace_size(C.byref(p), C.byref(n)) == lbm.LBM_E_INVAL
 
 
+def test_open_faces_validated(lib):
+    """An open (pressure) face of f needs a walled axis; unknown kinds and a
+    non-finite face pressure are rejected; the film with an open top passes."""
+    p = I.film2d_params(16, 8)
+    p["f_open"] = [[False, False], [False, True], [False, False]]
+    assert _status(p)[0] == lbm.LBM_OK
+    p["f_open"] = [[True, False], [False, False], [False, False]]   # x is periodic
+    assert _status(p)[0] == lbm.LBM_E_INVAL
+    assert b"walled axis" in lib.lbm_last_error()
+    q = lbm.make_params(I.film2d_params(16, 8), "f32")
+    q.f_bc[1][1] = 5
+    n = C.c_size_t()
+    assert lib.lbm_workspace_size(C.byref(q), C.byref(n)) == lbm.LBM_E_INVAL
+    q = lbm.make_params(I.film2d_params(16, 8), "f32")
+    q.f_bc[1][1] = lbm.LBM_FBC_PRESSURE
+    q.p_wall[1][1] = float("nan")
+    assert lib.lbm_workspace_size(C.byref(q), C.byref(n)) == lbm.LBM_E_INVAL
+
+
 def test_stream_probe_library_loads_and_checks_arguments():
     """The measurement probes bench.py times beside the step (their own
     library, outside the C ABI) are built, export their launchers, and
