@@ -52,8 +52,10 @@ typedef int32_t lbm_status;
 #define LBM_E_UNSUPPORTED (-6)  /* valid but not built (lattice/BC combo)   */
 
 /* Lattices (Sec. 3): D2Q9 in 2-D for f, g and s; in 3-D D3Q19 for f and
- * D3Q7 for g and s.  Stencils use D2Q9 in 2-D and D3Q19 in 3-D. */
-enum { LBM_D2Q9 = 9, LBM_D3Q7 = 7, LBM_D3Q19 = 19 };
+ * D3Q7 for g and s.  Stencils use D2Q9 in 2-D and D3Q19 in 3-D.  D2Q5
+ * (w = 1/2, 1/8; c_s^2 = 1/4), the z-projection of D3Q7, may carry g and s
+ * in 2-D (both): a z-invariant 3-D run then equals the 2-D run. */
+enum { LBM_D2Q9 = 9, LBM_D2Q5 = 5, LBM_D3Q7 = 7, LBM_D3Q19 = 19 };
 
 /* Population storage.  F16_DEV / BF16_DEV store each population as the
  * 16-bit float (value - w_i * ref) * 2^k with a power-of-two scale;

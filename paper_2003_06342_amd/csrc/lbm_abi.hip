@@ -124,8 +124,10 @@ lbm_status validate(const lbm_params* p) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_E_INVAL, "grid sizes must be >= 1");
   if (p->dim == 2) {
     if (p->nz != 1) return fail(LBM_E_INVAL, "2-D needs nz == 1");
-    if (p->lat_f != LBM_D2Q9 || p->lat_g != LBM_D2Q9 || p->lat_s != LBM_D2Q9)
-      return fail(LBM_E_UNSUPPORTED, "2-D supports D2Q9 for f, g and s");
+    if (p->lat_f != LBM_D2Q9 || (p->lat_g != LBM_D2Q9 && p->lat_g != LBM_D2Q5) ||
+        p->lat_s != p->lat_g)
+      return fail(LBM_E_UNSUPPORTED,
+                  "2-D supports D2Q9 for f and D2Q9 or D2Q5 (the same) for g and s");
     // the 2-halo ghost beyond a wall mirrors the second node from it
     if ((p->bc[0] == LBM_BC_WALL && p->nx < 2) || (p->bc[1] == LBM_BC_WALL && p->ny < 2))
       return fail(LBM_E_INVAL, "a walled axis needs at least 2 nodes");
@@ -237,6 +239,7 @@ KArgs<Real, Store> make_args(const lbm_ctx* c) {
   a.off_f = 0;
   a.off_g = c->L.Qf;
   a.off_s = c->L.Qf + c->L.Qg;
+  a.q_gs = c->L.Qg;
   for (int d = 0; d < 3; ++d)
     for (int s = 0; s < 2; ++s) {
       a.Tw[d][s] = (const Real*)c->tw[d][s];
@@ -249,7 +252,7 @@ KArgs<Real, Store> make_args(const lbm_ctx* c) {
     a.scale[k] = (Real)c->scale[k];
     a.inv_scale[k] = (Real)(1.0 / c->scale[k]);
   }
-  const double cs2g = p.dim == 2 ? 1.0 / 3.0 : 0.25;
+  const double cs2g = (p.dim == 2 && p.lat_g == LBM_D2Q9) ? 1.0 / 3.0 : 0.25;   // D3Q7, D2Q5: 1/4
   a.rho_l = (Real)p.rho_l;
   a.rho_g = (Real)p.rho_g;
   a.K = (Real)(1.5 * p.W * p.sigma);          // Eq. Def_K-H
@@ -648,6 +651,7 @@ lbm_status adjoint_supported(const lbm_ctx* c) {
   if (!c->ns || !c->heat) return fail(LBM_E_UNSUPPORTED, "adjoint needs LBM_NS | LBM_HEAT");
   if (p.bc[0] == LBM_BC_WALL && p.bc[1] == LBM_BC_WALL)
     return fail(LBM_E_UNSUPPORTED, "adjoint supports at most one walled axis");
+  if (p.lat_g != LBM_D2Q9) return fail(LBM_E_UNSUPPORTED, "adjoint is built for D2Q9 populations");
   if (p.collision != LBM_COLL_BGK) return fail(LBM_E_UNSUPPORTED, "adjoint is built for BGK collision");
   if (p.grad_scheme != LBM_GRAD_CENTRAL)
     return fail(LBM_E_UNSUPPORTED, "adjoint is built for central gradients");

@@ -41,6 +41,29 @@ struct D2Q9 {
   static constexpr double cs2 = 1.0 / 3.0;
 };
 
+// D2Q5: the z-projection of D3Q7 (w0 = 1/2, w = 1/8, c_s^2 = 1/4), for the
+// phase-field and heat populations of 2-D runs that cross-check the 3-D path.
+// Order: rest, +x, +y, -x, -y.
+struct D2Q5 {
+  static constexpr int Q = 5;
+  static constexpr int D = 2;
+  __host__ __device__ static constexpr int cx(int i) {
+    constexpr int v[5] = {0, 1, 0, -1, 0};
+    return v[i];
+  }
+  __host__ __device__ static constexpr int cy(int i) {
+    constexpr int v[5] = {0, 0, 1, 0, -1};
+    return v[i];
+  }
+  __host__ __device__ static constexpr int cz(int) { return 0; }
+  __host__ __device__ static constexpr int opp(int i) {
+    constexpr int v[5] = {0, 3, 4, 1, 2};
+    return v[i];
+  }
+  __host__ __device__ static constexpr double w(int i) { return i == 0 ? 0.5 : 0.125; }
+  static constexpr double cs2 = 0.25;
+};
+
 struct D3Q7 {
   static constexpr int Q = 7;
   static constexpr int D = 3;
@@ -139,6 +162,7 @@ struct KArgs {
   long long slab;         // px * ny * nz
   int wall[3];            // axis is walled (else periodic)
   int off_f, off_g, off_s;  // first population plane of each family
+  int q_gs;                 // populations of the phase-field (and heat) family
   // populations: read A, write B
   const Store* __restrict__ A;
   Store* __restrict__ B;
@@ -456,6 +480,25 @@ struct MrtBasis<D3Q7> {
   }
   __host__ __device__ static constexpr int rate(int, int k) {
     constexpr int r[7] = {0, 4, 4, 4, 0, 3, 3};
+    return r[k];
+  }
+};
+// D2Q5: 1, cx, cy, 5c^2 - 4, cx^2 - cy^2 (g and s).
+template <>
+struct MrtBasis<D2Q5> {
+  static constexpr bool ok = true;
+  __host__ __device__ static constexpr double M(int k, int i) {
+    const double cx = D2Q5::cx(i), cy = D2Q5::cy(i), c2 = cx * cx + cy * cy;
+    switch (k) {
+      case 0: return 1.0;
+      case 1: return cx;
+      case 2: return cy;
+      case 3: return 5.0 * c2 - 4.0;
+      default: return cx * cx - cy * cy;
+    }
+  }
+  __host__ __device__ static constexpr int rate(int, int k) {
+    constexpr int r[5] = {0, 4, 4, 0, 3};
     return r[k];
   }
 };

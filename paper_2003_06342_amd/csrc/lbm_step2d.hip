@@ -33,7 +33,8 @@ struct StepTile {
   static constexpr int NT = TY <= 16 ? TX2 * TY : 512;
 };
 
-template <class Store, class Real, bool NS, bool HEAT, int MODE, bool FAST, int TY, bool EXT, bool NTS>
+template <class Store, class Real, bool NS, bool HEAT, int MODE, bool FAST, int TY, bool EXT, bool NTS,
+          class LG>
 __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*sphi)[R1X],
                                             Real (*sux)[R2X], Real (*suy)[R2X], int x0, int y0) {
   using C = Codec<Real, Store>;
@@ -42,8 +43,8 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
   constexpr int NT = StepTile<TY>::NT;
   // the step keeps the g and f that phases 1-2 pulled for the lane's node
   constexpr bool CARRY = MODE == MODE_STEP && NT == TX2 * TY;
-  Real gk[9], fk[9];
-  stage2d<Store, Real, NS, HEAT, FAST, TY, NT, CARRY>(a, sphi, sux, suy, x0, y0, gk, fk);
+  Real gk[LG::Q], fk[9];
+  stage2d<Store, Real, NS, HEAT, FAST, TY, NT, CARRY, LG>(a, sphi, sux, suy, x0, y0, gk, fk);
 
   // ---- phase 3: the tile's nodes ------------------------------------------
   double acc_phi = 0, acc_T = 0, acc_phip = 0, acc_umax = 0, acc_bad = 0;
@@ -100,8 +101,8 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
     // One family live at a time: heat (gives T and q), then phi, then NS
     // (needs q for the pressure moment and the production source).
     if constexpr (HEAT) {
-      Real s[9];
-      gather2d<D2Q9, 2, FAST>(a, x, y, s);
+      Real s[LG::Q];
+      gather2d<LG, 2, FAST>(a, x, y, s);
       if constexpr (NS) {
         if constexpr (EXT || MODE == MODE_MACRO) {
           if (a.div_local)
@@ -114,34 +115,34 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
       }
       Real m0s = 0;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) m0s += s[i];
+      for (int i = 0; i < LG::Q; ++i) m0s += s[i];
       m.T = m0s - (Real)0.5 * a.Lcp * (m.dtphi + m.D);
       m.q = production(a, m.phi, m.T, m.alpha);
       if constexpr (MODE == MODE_STEP) {
-        const Real om = (Real)1 / (m.alpha * (Real)3 + (Real)0.5);
+        const Real om = (Real)1 / (m.alpha * (Real)(1.0 / LG::cs2) + (Real)0.5);   // alpha = tau c_s^2
         if constexpr (EXT)
-          collide_s_ext<D2Q9>(a, s, m, om);
+          collide_s_ext<LG>(a, s, m, om);
         else
-          collide_s<D2Q9>(a, s, m, om);
+          collide_s<LG>(a, s, m, om);
         // 16-bit storage: the s deviations are about this node's own T
         const Real Tref = kNodeRef<Real, Store> ? (Real)(Sc)m.T : a.ref[2];
-        store_family<D2Q9, NTS>(a, a.off_s, 2, node, s, Tref);
+        store_family<LG, NTS>(a, a.off_s, 2, node, s, Tref);
         if constexpr (kNodeRef<Real, Store>) st_plane<NTS>(a.B_Tref, node, (Sc)m.T);
       }
     }
     if constexpr (MODE == MODE_STEP) {
-      Real g[9];
+      Real g[LG::Q];
       if constexpr (CARRY) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = gk[i];
+        for (int i = 0; i < LG::Q; ++i) g[i] = gk[i];
       } else {
-        gather2d<D2Q9, 1, FAST>(a, x, y, g);
+        gather2d<LG, 1, FAST>(a, x, y, g);
       }
       if constexpr (EXT)
-        collide_g_ext<D2Q9>(a, g, m);
+        collide_g_ext<LG>(a, g, m);
       else
-        collide_g<D2Q9>(a, g, m);
-      store_family<D2Q9, NTS>(a, a.off_g, 1, node, g,
+        collide_g<LG>(a, g, m);
+      store_family<LG, NTS>(a, a.off_g, 1, node, g,
                          kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1]);
     }
     const Real cs2 = (Real)(1.0 / 3.0);
@@ -204,7 +205,7 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
   }
 }
 
-template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT, bool NTS>
+template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT, bool NTS, class LG>
 __device__ __forceinline__ void step2d_body(const KArgs<Real, Store>& a) {
   __shared__ Real sphi[Tile2<TY>::R1Y][R1X];
   __shared__ Real sux[Tile2<TY>::R2Y][R2X];
@@ -221,32 +222,32 @@ __device__ __forceinline__ void step2d_body(const KArgs<Real, Store>& a) {
   // lies inside the domain, so no wall link and no periodic wrap occurs
   const bool interior = x0 >= 3 && x0 + TX2 + 3 <= a.nx && y0 >= 3 && y0 + TY + 3 <= a.ny;
   if (interior)
-    step_tile2d<Store, Real, NS, HEAT, MODE, true, TY, EXT, NTS>(a, sphi, sux, suy, x0, y0);
+    step_tile2d<Store, Real, NS, HEAT, MODE, true, TY, EXT, NTS, LG>(a, sphi, sux, suy, x0, y0);
   else
-    step_tile2d<Store, Real, NS, HEAT, MODE, false, TY, EXT, NTS>(a, sphi, sux, suy, x0, y0);
+    step_tile2d<Store, Real, NS, HEAT, MODE, false, TY, EXT, NTS, LG>(a, sphi, sux, suy, x0, y0);
 }
 
 // EXT: the extended step (TRT / MRT collision, biased directional
 // derivatives, local div(u phi)), selected at run time from the arguments;
 // the default kernels are BGK with central derivatives.
-template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT, bool NTS>
+template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT, bool NTS, class LG>
 __global__ __launch_bounds__(StepTile<TY>::NT) void k_step2d(const KArgs<Real, Store> a) {
-  step2d_body<Store, Real, NS, HEAT, MODE, TY, EXT, NTS>(a);
+  step2d_body<Store, Real, NS, HEAT, MODE, TY, EXT, NTS, LG>(a);
 }
 
 // 16-bit storage: at most 128 VGPRs (4 waves per SIMD).  The codec constants
 // and per-node references pushed the 64-row tile kernel past that (0.200 ->
 // 0.136 ms at 1024 x 2048 with the cap); the 4-row carry kernel needs 72.
-template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT, bool NTS>
+template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT, bool NTS, class LG>
 __global__ __launch_bounds__(StepTile<TY>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_step2d_w4(
     const KArgs<Real, Store> a) {
-  step2d_body<Store, Real, NS, HEAT, MODE, TY, EXT, NTS>(a);
+  step2d_body<Store, Real, NS, HEAT, MODE, TY, EXT, NTS, LG>(a);
 }
 
 // Initialisation: populations = equilibrium - S/2 at the given fields with
 // d_t phi = 0 and div(u0 phi0) from u0; written as the pre-image of the pull
 // gather (each value goes to the slot the next gather reads it from).
-template <class Store, class Real, bool NS, bool HEAT>
+template <class Store, class Real, bool NS, bool HEAT, class LG>
 __global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, const void* phi0,
                                                 const void* T0, const void* u0, const void* p0,
                                                 int f64) {
@@ -339,16 +340,16 @@ __global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, cons
   }
   m.p = (NS && p0) ? ld(p0, 0, x, y) : (Real)0;
   const Real cs2 = (Real)(1.0 / 3.0);
-  // populations = eq - S/2, written out
-  Real f[9], g[9], s[9];
-  const Real a0 = gamma_huu<D2Q9>(m.u);
+  // populations = eq - S/2, written out: f on D2Q9, g and s on LG
+  Real f[9], g[LG::Q], s[LG::Q];
   const bool biased = a.grad_scheme != GRAD_CENTRAL;
-  for (int i = 0; i < 9; ++i) {
-    const Real w = (Real)D2Q9::w(i);
-    const Real G = gamma_i<D2Q9>(i, m.u, a0);
-    const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
-    const Real c[3] = {(Real)cx, (Real)cy, (Real)0};
-    if (NS) {
+  if (NS) {
+    const Real a0 = gamma_huu<D2Q9>(m.u);
+    for (int i = 0; i < 9; ++i) {
+      const Real w = (Real)D2Q9::w(i);
+      const Real G = gamma_i<D2Q9>(i, m.u, a0);
+      const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
+      const Real c[3] = {(Real)cx, (Real)cy, (Real)0};
       Real Ff = 0;
       if (biased) {
         // biased schemes: c_i . grad(phi) of the NS source is the
@@ -366,57 +367,66 @@ __global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, cons
       const Real S = Ff + w * m.rho * cs2 * m.q * a.prod_fac;
       f[i] = w * m.p + m.rho * cs2 * (G - w) - (Real)0.5 * S;
     }
-    const Real cn = c[0] * m.n[0] + c[1] * m.n[1];
-    const Real Fg = a.four_over_W * m.phi * ((Real)1 - m.phi) * w * cn;
-    const Real Pg = w * m.q;
-    g[i] = a.geq_cac ? m.phi * G + a.M_over_cs2g * Fg - (Real)0.5 * Pg
-                     : m.phi * G - (Real)0.5 * (Fg + Pg);
-    if (HEAT) s[i] = m.T * G - (Real)0.5 * (w * (-a.Lcp * (m.dtphi + m.D)));
   }
-  // scatter to the pre-image slots
-  for (int i = 0; i < 9; ++i) {
-    const int cx = D2Q9::cx(i), cy = D2Q9::cy(i);
-    int sx = x - cx, sy = y - cy;
-    const bool oy = cy != 0 && a.wall[1] && (sy < 0 || sy >= a.ny);
-    const bool ox = cx != 0 && !oy && a.wall[0] && (sx < 0 || sx >= a.nx);
-    const Real w = (Real)D2Q9::w(i);
-    if (oy || ox) {
-      const int j = D2Q9::opp(i);
-      const long long node = (long long)y * a.px + x;
-      Real Vg, Vs;
-      const int ax = oy ? 1 : 0;
-      const int side = oy ? (sy < 0 ? 0 : 1) : (sx < 0 ? 0 : 1);
-      Vg = a.phi_w[ax][side];
-      Vs = HEAT ? (oy ? a.Tw[1][side][x] : a.Tw[0][side][y]) : (Real)0;
-      // bounce-back returns the slot as is; an open face returns
-      // -slot + 2 w_i p_w, so its slot holds 2 w_i p_w - f_i
-      if (NS)
-        a.B[(long long)(a.off_f + j) * a.slab + node] =
-            C::enc(a.f_open[ax][side] ? (Real)2 * w * a.p_w[ax][side] - f[i] : f[i], w * a.ref[0],
-                   a.scale[0]);
-      const Real gr = kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1];   // slot at this node
-      a.B[(long long)(a.off_g + j) * a.slab + node] =
-          C::enc((Real)2 * w * Vg - g[i], w * gr, a.scale[1]);
-      if (HEAT) {
-        const Real tr = kNodeRef<Real, Store> ? (Real)(Sc)m.T : a.ref[2];   // slot at this node
-        a.B[(long long)(a.off_s + j) * a.slab + node] =
-            C::enc((Real)2 * w * Vs - s[i], w * tr, a.scale[2]);
-      }
-    } else {
-      if (!a.wall[0]) sx = wrap1(sx, a.nx);
-      if (!a.wall[1]) sy = wrap1(sy, a.ny);
-      const long long node = (long long)sy * a.px + sx;
-      if (NS) a.B[(long long)(a.off_f + i) * a.slab + node] = C::enc(f[i], w * a.ref[0], a.scale[0]);
-      // the slot belongs to node (sx, sy): its reference is that node's phi0
-      const Real gr = kNodeRef<Real, Store> ? (Real)(Sc)ld(phi0, 0, sx, sy) : a.ref[1];
-      a.B[(long long)(a.off_g + i) * a.slab + node] = C::enc(g[i], w * gr, a.scale[1]);
-      if (HEAT) {
-        // the slot belongs to node (sx, sy): its reference is that node's T0
-        const Real tr = kNodeRef<Real, Store> ? (Real)(Sc)ld(T0, 0, sx, sy) : a.ref[2];
-        a.B[(long long)(a.off_s + i) * a.slab + node] = C::enc(s[i], w * tr, a.scale[2]);
-      }
+  {
+    const Real a0 = gamma_huu<LG>(m.u);
+    for (int i = 0; i < LG::Q; ++i) {
+      const Real w = (Real)LG::w(i);
+      const Real G = gamma_i<LG>(i, m.u, a0);
+      const Real cn = (Real)LG::cx(i) * m.n[0] + (Real)LG::cy(i) * m.n[1];
+      const Real Fg = a.four_over_W * m.phi * ((Real)1 - m.phi) * w * cn;
+      const Real Pg = w * m.q;
+      g[i] = a.geq_cac ? m.phi * G + a.M_over_cs2g * Fg - (Real)0.5 * Pg
+                       : m.phi * G - (Real)0.5 * (Fg + Pg);
+      if (HEAT) s[i] = m.T * G - (Real)0.5 * (w * (-a.Lcp * (m.dtphi + m.D)));
     }
   }
+  // scatter to the pre-image slots: slot i of node x - c_i, or at a wall link
+  // slot i' of node x itself (it is read back reflected)
+  auto scatter = [&](auto lat, int fam, const Real* v) {
+    using L = decltype(lat);
+    const int off = fam == 0 ? a.off_f : (fam == 1 ? a.off_g : a.off_s);
+    for (int i = 0; i < L::Q; ++i) {
+      const int cx = L::cx(i), cy = L::cy(i);
+      int sx = x - cx, sy = y - cy;
+      const bool oy = cy != 0 && a.wall[1] && (sy < 0 || sy >= a.ny);
+      const bool ox = cx != 0 && !oy && a.wall[0] && (sx < 0 || sx >= a.nx);
+      const Real w = (Real)L::w(i);
+      if (oy || ox) {
+        const long long node = (long long)y * a.px + x;
+        const int ax = oy ? 1 : 0;
+        const int side = oy ? (sy < 0 ? 0 : 1) : (sx < 0 ? 0 : 1);
+        Real val, ref;
+        if (fam == 0) {
+          // bounce-back returns the slot as is; an open face returns
+          // -slot + 2 w_i p_w, so its slot holds 2 w_i p_w - f_i
+          val = a.f_open[ax][side] ? (Real)2 * w * a.p_w[ax][side] - v[i] : v[i];
+          ref = a.ref[0];
+        } else if (fam == 1) {
+          val = (Real)2 * w * a.phi_w[ax][side] - v[i];
+          ref = kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1];   // slot at this node
+        } else {
+          val = (Real)2 * w * (oy ? a.Tw[1][side][x] : a.Tw[0][side][y]) - v[i];
+          ref = kNodeRef<Real, Store> ? (Real)(Sc)m.T : a.ref[2];     // slot at this node
+        }
+        a.B[(long long)(off + L::opp(i)) * a.slab + node] = C::enc(val, w * ref, a.scale[fam]);
+      } else {
+        if (!a.wall[0]) sx = wrap1(sx, a.nx);
+        if (!a.wall[1]) sy = wrap1(sy, a.ny);
+        const long long node = (long long)sy * a.px + sx;
+        // the slot belongs to node (sx, sy): its reference is that node's
+        // phi0 (g) or T0 (s)
+        const Real ref = fam == 0 ? a.ref[0]
+                                  : (kNodeRef<Real, Store>
+                                         ? (Real)(Sc)ld(fam == 1 ? phi0 : T0, 0, sx, sy)
+                                         : a.ref[fam]);
+        a.B[(long long)(off + i) * a.slab + node] = C::enc(v[i], w * ref, a.scale[fam]);
+      }
+    }
+  };
+  if (NS) scatter(D2Q9{}, 0, f);
+  scatter(LG{}, 1, g);
+  if (HEAT) scatter(LG{}, 2, s);
   const long long node = (long long)y * a.px + x;
   a.B_phip[node] = (Sc)m.phi;
   a.B_qp[node] = (Sc)m.q;
@@ -441,27 +451,35 @@ static hipError_t launch_step2d_t(const KArgs<Real, Store>& a, int ns, int heat,
   constexpr bool small_tiles = st16 || sizeof(Store) == 8;
   const int ty = mode != MODE_STEP ? 64 : (small_tiles ? 4 : 16);
   const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + ty - 1) / ty);
-  const bool ext = a.coll != COLL_BGK || a.grad_scheme != GRAD_CENTRAL || a.div_local;
-#define LBM_K(NSV, HV, MV, TYV, EV, NTV)                                                        \
+  // D2Q5 phase-field and heat populations run the extended kernels
+  const bool d2q5 = a.q_gs == 5;
+  const bool ext = a.coll != COLL_BGK || a.grad_scheme != GRAD_CENTRAL || a.div_local || d2q5;
+#define LBM_K(NSV, HV, MV, TYV, EV, NTV, LGV)                                                   \
   do {                                                                                          \
     if constexpr (st16)                                                                         \
-      hipLaunchKernelGGL((k_step2d_w4<Store, Real, NSV, HV, MV, TYV, EV, NTV>), dim3(tiles),   \
+      hipLaunchKernelGGL((k_step2d_w4<Store, Real, NSV, HV, MV, TYV, EV, NTV, LGV>), dim3(tiles), \
                          dim3(StepTile<TYV>::NT), 0, st, a);                                    \
     else                                                                                        \
-      hipLaunchKernelGGL((k_step2d<Store, Real, NSV, HV, MV, TYV, EV, NTV>), dim3(tiles),      \
+      hipLaunchKernelGGL((k_step2d<Store, Real, NSV, HV, MV, TYV, EV, NTV, LGV>), dim3(tiles),  \
                          dim3(StepTile<TYV>::NT), 0, st, a);                                    \
   } while (0)
 // the default step with or without non-temporal stores; the extended step
-// with plain stores
-#define LBM_L(NSV, HV, MV, TYV)                         \
-  do {                                                  \
-    if (ext) LBM_K(NSV, HV, MV, TYV, true, false);      \
-    else if (a.nt) LBM_K(NSV, HV, MV, TYV, false, true); \
-    else LBM_K(NSV, HV, MV, TYV, false, false);         \
+// with plain stores, on D2Q9 or D2Q5 phase-field and heat populations
+#define LBM_L(NSV, HV, MV, TYV)                                 \
+  do {                                                          \
+    if (ext && d2q5) LBM_K(NSV, HV, MV, TYV, true, false, D2Q5); \
+    else if (ext) LBM_K(NSV, HV, MV, TYV, true, false, D2Q9);   \
+    else if (a.nt) LBM_K(NSV, HV, MV, TYV, false, true, D2Q9);  \
+    else LBM_K(NSV, HV, MV, TYV, false, false, D2Q9);           \
   } while (0)
 #define LBM_L2(NSV, HV, MV)                \
   if constexpr (small_tiles) LBM_L(NSV, HV, MV, 4); \
   else LBM_L(NSV, HV, MV, 16)
+#define LBM_M(NSV, HV)                                                \
+  do {                                                                \
+    if (d2q5) LBM_K(NSV, HV, MODE_MACRO, 64, false, false, D2Q5);     \
+    else LBM_K(NSV, HV, MODE_MACRO, 64, false, false, D2Q9);          \
+  } while (0)
   if (mode == MODE_STEP) {
     if (ns && heat) { LBM_L2(true, true, MODE_STEP); }
     else if (ns) { LBM_L2(true, false, MODE_STEP); }
@@ -469,11 +487,12 @@ static hipError_t launch_step2d_t(const KArgs<Real, Store>& a, int ns, int heat,
     else { LBM_L2(false, false, MODE_STEP); }
   } else {
     // the fields pass takes the local div(u phi) at run time
-    if (ns && heat) LBM_K(true, true, MODE_MACRO, 64, false, false);
-    else if (ns) LBM_K(true, false, MODE_MACRO, 64, false, false);
-    else if (heat) LBM_K(false, true, MODE_MACRO, 64, false, false);
-    else LBM_K(false, false, MODE_MACRO, 64, false, false);
+    if (ns && heat) LBM_M(true, true);
+    else if (ns) LBM_M(true, false);
+    else if (heat) LBM_M(false, true);
+    else LBM_M(false, false);
   }
+#undef LBM_M
 #undef LBM_L2
 #undef LBM_L
 #undef LBM_K
@@ -485,8 +504,15 @@ static hipError_t launch_init2d_t(const KArgs<Real, Store>& a, int ns, int heat,
                                   const void* T0, const void* u0, const void* p0, int f64,
                                   hipStream_t st) {
   dim3 block(256), grid((a.nx + 255) / 256, a.ny);
-#define LBM_I(NSV, HV) \
-  hipLaunchKernelGGL((k_init2d<Store, Real, NSV, HV>), grid, block, 0, st, a, phi0, T0, u0, p0, f64)
+#define LBM_I(NSV, HV)                                                                          \
+  do {                                                                                          \
+    if (a.q_gs == 5)                                                                            \
+      hipLaunchKernelGGL((k_init2d<Store, Real, NSV, HV, D2Q5>), grid, block, 0, st, a, phi0, T0, \
+                         u0, p0, f64);                                                          \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_init2d<Store, Real, NSV, HV, D2Q9>), grid, block, 0, st, a, phi0, T0, \
+                         u0, p0, f64);                                                          \
+  } while (0)
   if (ns && heat) LBM_I(true, true);
   else if (ns) LBM_I(true, false);
   else if (heat) LBM_I(false, true);

@@ -200,7 +200,7 @@ __device__ __forceinline__ void halo2_rc(int h, int& ry, int& rx) {
 // gk and the f it pulled for u in fk, so the node update does not pull them
 // again; the halo nodes follow.
 template <class Store, class Real, bool NS, bool HEAT, bool FAST, int TY = TY2,
-          int NT = Tile2<TY>::NT, bool CARRY = false>
+          int NT = Tile2<TY>::NT, bool CARRY = false, class LG = D2Q9>
 __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi)[R1X],
                                         Real (*sux)[R2X], Real (*suy)[R2X], int x0, int y0,
                                         Real* gk = nullptr, Real* fk = nullptr) {
@@ -211,10 +211,10 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
     int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
     Real v = 0;
     if (FAST || (to_domain(gx, a.nx, a.wall[0]) && to_domain(gy, a.ny, a.wall[1]))) {
-      gather2d<D2Q9, 1, FAST>(a, gx, gy, g);
+      gather2d<LG, 1, FAST>(a, gx, gy, g);
       Real s = 0;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) s += g[i];
+      for (int i = 0; i < LG::Q; ++i) s += g[i];
       v = s + (Real)0.5 * (Real)ld_plane(a.A_qp, (unsigned)(gy * a.px + gx));
     }
     sphi[ry][rx] = v;
@@ -224,13 +224,13 @@ __device__ __forceinline__ void stage2d(const KArgs<Real, Store>& a, Real (*sphi
     for (int h = tid; h < R1X * Tile2<TY>::R1Y - TX2 * TY; h += NT) {
       int ry, rx;
       halo1_rc<TY>(h, ry, rx);
-      Real g[9];
+      Real g[LG::Q];
       phi_node(ry, rx, g);
     }
   } else {
     for (int k = tid; k < R1X * Tile2<TY>::R1Y; k += NT) {
       const int ry = k / R1X, rx = k - ry * R1X;
-      Real g[9];
+      Real g[LG::Q];
       phi_node(ry, rx, g);
     }
   }

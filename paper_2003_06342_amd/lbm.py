@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_STATE, LBM_E_UNSTABLE, LBM_E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-LBM_D2Q9, LBM_D3Q7, LBM_D3Q19 = 9, 7, 19
+LBM_D2Q9, LBM_D2Q5, LBM_D3Q7, LBM_D3Q19 = 9, 5, 7, 19
 ST = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3}
 LBM_BC_PERIODIC, LBM_BC_WALL = 0, 1
 LBM_NS, LBM_HEAT, LBM_PHASE_CHANGE, LBM_VISC_LINEAR, LBM_GEQ_CAC, LBM_DIV_LOCAL = \
@@ -31,7 +31,7 @@ LBM_DT_F32, LBM_DT_F64 = 0, 1
 LBM_FBC_NOSLIP, LBM_FBC_PRESSURE = 0, 1
 LBM_STATIC_SCRATCH_BYTES = 128 << 20   # include/lbm.h
 FIELDS = ["phi", "p", "ux", "uy", "uz", "T"]          # bit order of LBM_FIELD_*
-LAT = {"D2Q9": LBM_D2Q9, "D3Q7": LBM_D3Q7, "D3Q19": LBM_D3Q19}
+LAT = {"D2Q9": LBM_D2Q9, "D2Q5": LBM_D2Q5, "D3Q7": LBM_D3Q7, "D3Q19": LBM_D3Q19}
 
 
 class LBMError(RuntimeError):

@@ -194,3 +194,20 @@ def test_stream_probe_library_loads_and_checks_arguments():
     assert g(None, None, 1024, 0, None) != 0
     assert g(C.c_void_p(16), C.c_void_p(32), 1000, 0, None) != 0   # not a multiple of 16
     assert g(C.c_void_p(8), C.c_void_p(32), 1024, 1, None) != 0    # misaligned source
+
+
+def test_d2q5_lattice_validated(lib):
+    """2-D takes D2Q5 for g and s (the same for both; f stays D2Q9), and the
+    workspace holds 9 + 5 + 5 populations; mixed or 3-D use is rejected."""
+    p = I.film2d_params(130, 66, lat_g="D2Q5", lat_s="D2Q5")
+    st, n = _status(p)
+    assert st == lbm.LBM_OK
+    assert n >= 2 * 19 * 192 * 66 * 4
+    assert n < _status(I.film2d_params(130, 66))[1]
+    p["lat_s"] = "D2Q9"
+    assert _status(p)[0] == lbm.LBM_E_UNSUPPORTED
+    p = I.film2d_params(16, 8, lat_f="D2Q5", lat_g="D2Q5", lat_s="D2Q5")
+    assert _status(p)[0] == lbm.LBM_E_UNSUPPORTED
+    p3 = I.film3d_params(32, nz=24)
+    p3["lat_g"] = "D2Q5"
+    assert _status(p3)[0] == lbm.LBM_E_UNSUPPORTED

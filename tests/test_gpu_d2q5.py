@@ -1,0 +1,109 @@
+"""GPU parity of the 2-D path with D2Q5 phase-field and heat populations (the
+z-projection of D3Q7; f stays on D2Q9) against the FP64 oracle, and the
+z-invariance property through the library: a 3-D run (D3Q19 f, D3Q7 g and s,
+D3Q19 stencils) on z-invariant data equals the 2-D D2Q5 run in every z
+plane.  FP64 within 1e-10 (1e-12 for the GPU-to-GPU comparison), FP32 within
+max(1e-5, 3 x the float32 floor)."""
+import numpy as np
+import pytest
+
+from paper_2003_06342_amd import inputs as I
+from tests._parity import (compare, fp32_bars, fp32_floor, gpu_run, need_gpu, oracle_run, say)
+
+pytestmark = pytest.mark.gpu
+
+Q5 = dict(lat_g="D2Q5", lat_s="D2Q5")
+
+
+def _film(nx=130, ny=66, **kw):
+    prm = I.film2d_params(nx, ny, **Q5)
+    prm["gravity"] = [0.0, -2e-5, 0.0]
+    prm.update(kw)
+    phi0, T0, _ = I.film2d_fields(prm, seed=0, h0=12.0, amp=2.0)
+    return prm, phi0, T0
+
+
+def _keys(prm):
+    return ["phi"] + (["T"] if prm["heat"] else []) + (["umag", "p"] if prm["ns"] else [])
+
+
+def _check(name, prm, phi0, T0, n, storage, tol, u0=None):
+    need_gpu()
+    say(f"[d2q5] {name}: storage={storage} steps={n}")
+    ref = oracle_run(prm, phi0, T0, n, u0=u0)
+    gpu = gpu_run(prm, phi0, T0, n, storage, u0=u0)
+    errs = compare(gpu, ref)
+    say(f"[d2q5] {name}: errors {errs}")
+    for k in _keys(prm):
+        assert errs[k] <= tol, (k, errs)
+    return gpu, ref
+
+
+def test_film2d_d2q5_f64():
+    prm, phi0, T0 = _film()
+    gpu, ref = _check("film2d", prm, phi0, T0, 60, "f64", 1e-10)
+    assert abs(gpu["diag"]["mass"] - ref["diag"]["mass"]) <= 1e-9 * abs(ref["diag"]["mass"])
+
+
+def test_film2d_d2q5_initial_velocity_f64():
+    prm, phi0, T0 = _film()
+    ny, nx = phi0.shape[1:]
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    ux = 1e-3 * np.sin(2 * np.pi * x)[None, :] * np.sin(np.pi * y)[:, None]
+    uy = 1e-3 * np.cos(2 * np.pi * x)[None, :] * np.sin(np.pi * y)[:, None]
+    u0 = [ux[None], uy[None], np.zeros_like(ux)[None]]
+    _check("film2d_u0", prm, phi0, T0, 20, "f64", 1e-10, u0=u0)
+
+
+def test_film2d_d2q5_mrt_biased_f64():
+    prm, phi0, T0 = _film(collision="mrt", grad_scheme="biased2")
+    _check("film2d_mrt_biased2", prm, phi0, T0, 40, "f64", 1e-10)
+
+
+def test_heat_only_d2q5_f64():
+    prm, phi0, T0 = _film(ns=False)
+    _check("phase_heat_no_ns", prm, phi0, T0, 60, "f64", 1e-10)
+
+
+def test_film2d_d2q5_f32():
+    prm, phi0, T0 = _film()
+    need_gpu()
+    floor, ref = fp32_floor(prm, phi0, T0, 100)
+    gpu = gpu_run(prm, phi0, T0, 100, "f32")
+    errs = compare(gpu, ref)
+    bars = fp32_bars(floor)
+    say(f"[d2q5] film2d f32: gpu {errs} | fp32 floor {floor}")
+    for k in _keys(prm):
+        assert errs[k] <= bars[k], (k, errs, floor)
+
+
+def test_invariant_3d_equals_2d_d2q5_on_gpu():
+    """A 3-D film invariant along y (x, y periodic, walls on z) equals the 2-D
+    D2Q5 film (x periodic, walls on y) in every y plane, both on the GPU, with
+    2-D y read as 3-D z; the 2-D run also matches the oracle."""
+    need_gpu()
+    nx, ny, n3 = 70, 34, 4
+    p2 = I.film2d_params(nx, ny, **Q5)
+    p2["gravity"] = [0.0, -2e-5, 0.0]
+    p3 = I.film3d_params(nx, nz=ny, ny=n3)
+    p3["gravity"] = [0.0, 0.0, -2e-5]
+    phi0, T0, _ = I.film2d_fields(p2, seed=1, h0=8.0, amp=1.5)
+    lift = lambda a: np.repeat(a.transpose(1, 0, 2), n3, axis=1)   # (1,ny,nx) -> (ny,n3,nx)
+    n = 50
+    say(f"[d2q5] invariance: 2-D {nx}x{ny} vs 3-D {nx}x{n3}x{ny}, {n} steps, f64")
+    g2 = gpu_run(p2, phi0, T0, n, "f64")
+    g3 = gpu_run(p3, lift(phi0), lift(T0), n, "f64")
+    worst = 0.0
+    for k3, k2 in (("phi", "phi"), ("T", "T"), ("p", "p"), ("ux", "ux"), ("uz", "uy")):
+        for y in range(n3):
+            worst = max(worst, float(np.abs(g3[k3][:, y, :] - g2[k2][0]).max()))
+    say(f"[d2q5] invariance: max |3-D - 2-D| {worst:.3e}, max |uy| {np.abs(g3['uy']).max():.3e}")
+    assert worst <= 1e-12
+    assert float(np.abs(g3["uy"]).max()) <= 1e-14
+    assert float(np.abs(g2["uy"]).max()) > 1e-5
+    ref = oracle_run(p2, phi0, T0, n)
+    errs = compare(g2, ref)
+    say(f"[d2q5] invariance 2-D vs oracle: {errs}")
+    for k in ("phi", "T", "umag", "p"):
+        assert errs[k] <= 1e-10, (k, errs)
