@@ -324,7 +324,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_entry("k_step2d_film1024x2048_f32", head["nodes"]),
-                     "kernel": "k_step2d<float,float,NS,HEAT,STEP,16,EXT=false,NTS=true>",
+                     "kernel": "k_step2d<float,float,NS,HEAT,STEP,16,EXT=false,NTS=true,D2Q9>",
                      "bytes_per_node": bpn, "kernel_ms": round(head["kernel_ms"], 5)},
         "context": {"paper_K80_MLUPS_1024x1024": 80.96, "paper_Xeon16c_MLUPS_1024x1024": 11.97},
     }

@@ -246,6 +246,8 @@ KArgs<Real, Store> make_args(const lbm_ctx* c) {
       a.phi_w[d][s] = (Real)p.phi_wall[d][s];
       a.f_open[d][s] = p.f_bc[d][s] == LBM_FBC_PRESSURE ? 1 : 0;
       a.p_w[d][s] = (Real)p.p_wall[d][s];
+      a.f_sg[d][s] = a.f_open[d][s] ? (Real)-1 : (Real)1;
+      a.f_pw2[d][s] = a.f_open[d][s] ? (Real)2 * a.p_w[d][s] : (Real)0;
     }
   for (int k = 0; k < 3; ++k) {
     a.ref[k] = (Real)c->ref[k];

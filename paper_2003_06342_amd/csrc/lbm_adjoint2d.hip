@@ -112,9 +112,9 @@ __global__ __launch_bounds__(Tile2<TY>::NT) __attribute__((amdgpu_waves_per_eu(2
     if (x >= a.nx || y >= a.ny) continue;
     const unsigned node = (unsigned)(y * a.px + x);
     NodeIn<Real> in;
-    gather2d<D2Q9, 0, false>(a, x, y, in.Pf);
-    gather2d<D2Q9, 1, false>(a, x, y, in.Pg);
-    gather2d<D2Q9, 2, false>(a, x, y, in.Ps);
+    gather2d<D2Q9, 0, false, true>(a, x, y, in.Pf);
+    gather2d<D2Q9, 1, false, true>(a, x, y, in.Pg);
+    gather2d<D2Q9, 2, false, true>(a, x, y, in.Ps);
     in.phi = sphi[r + 2][lx + 2];
     Real g3[3];
     stencil2d<Real, R1X>(sphi, r + 2, lx + 2, g3, in.lphi);
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(256) void k_adj_init_local2d(const KArgs<Real, Real
   g[1] *= (Real)3;
   const Real lap = (l - (Real)2 * ws * phi) * (Real)6;
   Real Ps[9];
-  gather2d<D2Q9, 2, false>(a, x, y, Ps);
+  gather2d<D2Q9, 2, false, true>(a, x, y, Ps);
   Real T = 0;
   for (int i = 0; i < 9; ++i) T += Ps[i];
   Real l_phi, l_g[2], l_lap, l_T;

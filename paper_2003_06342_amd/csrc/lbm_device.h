@@ -177,9 +177,12 @@ struct KArgs {
   // per-node wall temperature on each walled face: [axis][side]
   const Real* __restrict__ Tw[3][2];
   Real phi_w[3][2];
-  // open (pressure) faces of f: pressure anti-bounce-back at p_w
+  // open (pressure) faces of f: pressure anti-bounce-back at p_w.  The
+  // gathers apply a wall link of f as f_sg r + w_i f_pw2 without a branch:
+  // (1, 0) on a no-slip face, (-1, 2 p_w) on an open one
   int f_open[3][2];
   Real p_w[3][2];
+  Real f_sg[3][2], f_pw2[3][2];
   // codec constants per family (f, g, s)
   Real ref[3], scale[3], inv_scale[3];
   // physics

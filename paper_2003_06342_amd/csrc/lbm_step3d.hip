@@ -40,7 +40,10 @@ __device__ inline int slot3(int p) { return (p + 9) % NU; }
 
 // Pull the Q populations of family FAM arriving at node (x, y, z); z walls
 // reflect at the node (bounce-back f, anti-bounce-back g, s).  XYIN: the
-// caller guarantees no x/y source crosses the periodic seam.
+// caller guarantees no x/y source crosses the periodic seam.  A link that
+// crosses a z wall (c_z = +1 at z = 0, c_z = -1 at z = nz - 1) reads the
+// opposite slot of the node itself; slot and transform are selected, not
+// branched on, so the loads of all Q links issue back to back.
 template <class Lat, int FAM, bool XYIN, class Real, class Store>
 __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z, Real* v) {
   using C = Codec<Real, Store>;
@@ -52,40 +55,43 @@ __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z
   // 16-bit storage: g and s are deviations from w_i phi(src) and w_i T_ref(src)
   constexpr bool NREF = FAM != 0 && kNodeRef<Real, Store>;
   const typename KArgs<Real, Store>::Sc* __restrict__ rplane = FAM == 1 ? a.A_phip : a.A_Tref;
+  // this plane's wall links (uniform) and the family's wall values
+  const bool wlo = a.wall[2] && z == 0, whi = a.wall[2] && z == a.nz - 1;
+  Real V[2] = {(Real)0, (Real)0};
+  if constexpr (FAM == 1) {
+    V[0] = a.phi_w[2][0];
+    V[1] = a.phi_w[2][1];
+  } else if constexpr (FAM == 2) {
+    if (wlo) V[0] = a.Tw[2][0][y * a.nx + x];
+    if (whi) V[1] = a.Tw[2][1][y * a.nx + x];
+  }
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
     const int cx = Lat::cx(i), cy = Lat::cy(i), cz = Lat::cz(i);
-    const Real wref = (Real)Lat::w(i) * ref;
-    int sz = z - cz;
-    const bool oz = (cz != 0) && a.wall[2] && (sz < 0 || sz >= a.nz);
-    if (oz) {
-      const int j = Lat::opp(i);
-      const Real wr = NREF ? (Real)Lat::w(i) * (Real)rplane[node] : wref;
-      Real r = C::dec((base + (size_t)j * (size_t)a.slab)[node], wr, inv);
-      const int side = sz < 0 ? 0 : 1;
-      if (FAM != 0) {
-        const Real V = FAM == 1 ? a.phi_w[2][side] : a.Tw[2][side][y * a.nx + x];
-        r = -r + (Real)2 * (Real)Lat::w(i) * V;
-      } else if (a.f_open[2][side]) {   // open face: pressure anti-bounce-back
-        r = -r + (Real)2 * (Real)Lat::w(i) * a.p_w[2][side];
-      }
-      v[i] = r;
+    const bool oz = cz > 0 ? wlo : (cz < 0 ? whi : false);
+    const int side = cz > 0 ? 0 : 1;
+    unsigned src;
+    if (XYIN) {
+      int dz = -cz;
+      if (cz != 0 && !a.wall[2]) dz = wrap1(z - cz, a.nz) - z;
+      src = (unsigned)((int)node - cx - cy * a.px + dz * pz);
     } else {
+      int sx = x - cx, sy = y - cy, sz = z - cz;
+      if (cx != 0) sx = wrap1(sx, a.nx);
+      if (cy != 0) sy = wrap1(sy, a.ny);
       if (cz != 0 && !a.wall[2]) sz = wrap1(sz, a.nz);
-      if (XYIN) {
-        const Store* __restrict__ p = base + (size_t)i * (size_t)a.slab;
-        const unsigned src = (unsigned)((int)node - cx - cy * a.px + (sz - z) * pz);
-        const Real wr = NREF ? (Real)Lat::w(i) * (Real)rplane[src] : wref;
-        v[i] = C::dec(p[src], wr, inv);
-      } else {
-        int sx = x - cx, sy = y - cy;
-        if (cx != 0) sx = wrap1(sx, a.nx);
-        if (cy != 0) sy = wrap1(sy, a.ny);
-        const unsigned src = (unsigned)(sz * pz + sy * a.px + sx);
-        const Real wr = NREF ? (Real)Lat::w(i) * (Real)rplane[src] : wref;
-        v[i] = C::dec((base + (size_t)i * (size_t)a.slab)[src], wr, inv);
-      }
+      src = (unsigned)(sz * pz + sy * a.px + sx);
     }
+    const int slot = oz ? Lat::opp(i) : i;
+    const unsigned at = oz ? node : src;
+    const Real wr = NREF ? (Real)Lat::w(i) * (Real)rplane[at] : (Real)Lat::w(i) * ref;
+    const Real r = C::dec((base + (size_t)slot * (size_t)a.slab)[at], wr, inv);
+    Real rw;
+    if constexpr (FAM != 0)
+      rw = -r + (Real)2 * (Real)Lat::w(i) * V[side];
+    else   // bounce-back, or pressure anti-bounce-back on an open face
+      rw = a.f_sg[2][side] * r + (Real)Lat::w(i) * a.f_pw2[2][side];
+    v[i] = oz ? rw : r;
   }
 }
 

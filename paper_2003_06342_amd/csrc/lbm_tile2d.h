@@ -27,7 +27,9 @@ struct Tile2 {
 // FAST: the caller guarantees that no source node of this tile lies beyond
 // a wall or across a periodic seam, so every pull is the uniform plane
 // pointer shifted by -(c_x + c_y px) and indexed by the node's lane offset.
-template <class Lat, int FAM, bool FAST = false, class Real, class Store>
+// BRANCH (the adjoint's local kernel, which runs only with no-slip faces of
+// f): each wall link branches to its reflected read; f links bounce back.
+template <class Lat, int FAM, bool FAST = false, bool BRANCH = false, class Real, class Store>
 __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real* v) {
   using C = Codec<Real, Store>;
   const int off = FAM == 0 ? a.off_f : (FAM == 1 ? a.off_g : a.off_s);
@@ -48,33 +50,77 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
     }
     return;
   }
+  if constexpr (BRANCH) {
+#pragma unroll
+    for (int i = 0; i < Lat::Q; ++i) {
+      const int cx = Lat::cx(i), cy = Lat::cy(i);
+      int sx = x - cx, sy = y - cy;
+      const bool oy = (cy != 0) && a.wall[1] && (sy < 0 || sy >= a.ny);
+      const bool ox = (cx != 0) && !oy && a.wall[0] && (sx < 0 || sx >= a.nx);
+      if (oy || ox) {
+        const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, node) : (Real)Lat::w(i) * ref;
+        Real r = C::dec(ld_fam(base, (unsigned)Lat::opp(i) * (unsigned)a.slab + node), wr, inv);
+        if (FAM != 0) {
+          const int side = oy ? (sy < 0 ? 0 : 1) : (sx < 0 ? 0 : 1);
+          const Real V = FAM == 1 ? (oy ? a.phi_w[1][side] : a.phi_w[0][side])
+                                  : (oy ? a.Tw[1][side][x] : a.Tw[0][side][y]);
+          r = -r + (Real)2 * (Real)Lat::w(i) * V;
+        }
+        v[i] = r;
+      } else {
+        if (cx != 0 && !a.wall[0]) sx = wrap1(sx, a.nx);
+        if (cy != 0 && !a.wall[1]) sy = wrap1(sy, a.ny);
+        const unsigned src = (unsigned)(sy * a.px + sx);
+        const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, src) : (Real)Lat::w(i) * ref;
+        v[i] = C::dec(ld_fam(base, (unsigned)i * (unsigned)a.slab + src), wr, inv);
+      }
+    }
+    return;
+  }
+  // wall values of the node's links: only a node next to a wall has any
+  // (per-node wall temperatures are loaded once here, not per link)
+  Real Vy[2] = {(Real)0, (Real)0}, Vx[2] = {(Real)0, (Real)0};
+  if constexpr (FAM == 1) {
+    Vy[0] = a.phi_w[1][0];
+    Vy[1] = a.phi_w[1][1];
+    Vx[0] = a.phi_w[0][0];
+    Vx[1] = a.phi_w[0][1];
+  } else if constexpr (FAM == 2) {
+    if (a.wall[1]) {
+      if (y == 0) Vy[0] = a.Tw[1][0][x];
+      if (y == a.ny - 1) Vy[1] = a.Tw[1][1][x];
+    }
+    if (a.wall[0]) {
+      if (x == 0) Vx[0] = a.Tw[0][0][y];
+      if (x == a.nx - 1) Vx[1] = a.Tw[0][1][y];
+    }
+  }
+  // a wall link reads the opposite slot of the node itself; slot, address and
+  // transform are selected, not branched on, so the Q loads issue together
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i) {
     const int cx = Lat::cx(i), cy = Lat::cy(i);
     int sx = x - cx, sy = y - cy;
     const bool oy = (cy != 0) && a.wall[1] && (sy < 0 || sy >= a.ny);
     const bool ox = (cx != 0) && !oy && a.wall[0] && (sx < 0 || sx >= a.nx);
-    const Real wref = (Real)Lat::w(i) * ref;
-    if (oy || ox) {
-      const int j = Lat::opp(i);
-      const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, node) : wref;
-      Real r = C::dec(ld_fam(base, (unsigned)j * (unsigned)a.slab + node), wr, inv);
-      const int ax = oy ? 1 : 0;
-      const int side = oy ? (sy < 0 ? 0 : 1) : (sx < 0 ? 0 : 1);
-      if (FAM != 0) {
-        const Real V = FAM == 1 ? a.phi_w[ax][side] : (oy ? a.Tw[1][side][x] : a.Tw[0][side][y]);
-        r = -r + (Real)2 * (Real)Lat::w(i) * V;
-      } else if (a.f_open[ax][side]) {   // open face: pressure anti-bounce-back
-        r = -r + (Real)2 * (Real)Lat::w(i) * a.p_w[ax][side];
-      }
-      v[i] = r;
-    } else {
-      if (cx != 0 && !a.wall[0]) sx = wrap1(sx, a.nx);
-      if (cy != 0 && !a.wall[1]) sy = wrap1(sy, a.ny);
-      const unsigned src = (unsigned)(sy * a.px + sx);
-      const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, src) : wref;
-      v[i] = C::dec(ld_fam(base, (unsigned)i * (unsigned)a.slab + src), wr, inv);
+    const bool o = oy || ox;
+    if (cx != 0 && !a.wall[0]) sx = wrap1(sx, a.nx);
+    if (cy != 0 && !a.wall[1]) sy = wrap1(sy, a.ny);
+    const unsigned at = o ? node : (unsigned)(sy * a.px + sx);
+    const int slot = o ? Lat::opp(i) : i;
+    const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, at) : (Real)Lat::w(i) * ref;
+    const Real r = C::dec(ld_fam(base, (unsigned)slot * (unsigned)a.slab + at), wr, inv);
+    // the crossed face: y (precedence at corners) or x, side from the sign of c
+    const int ys = cy > 0 ? 0 : 1, xs = cx > 0 ? 0 : 1;
+    Real rw;
+    if constexpr (FAM != 0) {
+      rw = -r + (Real)2 * (Real)Lat::w(i) * (oy ? Vy[ys] : Vx[xs]);
+    } else {   // bounce-back, or pressure anti-bounce-back on an open face
+      const Real sg = oy ? a.f_sg[1][ys] : a.f_sg[0][xs];
+      const Real pw2 = oy ? a.f_pw2[1][ys] : a.f_pw2[0][xs];
+      rw = sg * r + (Real)Lat::w(i) * pw2;
     }
+    v[i] = o ? rw : r;
   }
 }
 
