@@ -147,7 +147,12 @@ template <> struct ScalarOf<double> { using T = double; };
 // 16-bit storage keeps the s family as deviations from w_i T_ref(x), with
 // T_ref(x) the temperature of the node x that stored the population (one
 // scalar plane, written with the populations).  A slot (i, x) is always
-// encoded and decoded against T_ref(x), so pull and store agree.
+// encoded and decoded against T_ref(x), so pull and store agree.  The g
+// family is kept as deviations from w_i phi(y), with y = x + c_i the node
+// that reads slot (i, x) at the next step (x itself where x + c_i lies
+// beyond a wall): the writer takes phi(y) from its LDS tile, the reader its
+// own phi_prev, which is the same value.  A gather then needs one reference
+// per node instead of one per link.
 template <class Real, class Store>
 constexpr bool kNodeRef = !std::is_same<Real, Store>::value;
 

@@ -142,8 +142,22 @@ __device__ __forceinline__ void step_tile2d(const KArgs<Real, Store>& a, Real (*
         collide_g_ext<LG>(a, g, m);
       else
         collide_g<LG>(a, g, m);
-      store_family<LG, NTS>(a, a.off_g, 1, node, g,
-                         kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1]);
+      if constexpr (kNodeRef<Real, Store>) {
+        // slot i is read by x + c_i and decoded against that node's phi
+        // (its phi_prev next step, in LDS now); where x + c_i lies beyond a
+        // wall, x reads the slot back itself
+        store_family_ref<LG, NTS>(a, a.off_g, 1, node, g, [&](int i) -> Real {
+          const int cx = LG::cx(i), cy = LG::cy(i);
+          if (!FAST) {
+            const bool out = (cx != 0 && a.wall[0] && (x + cx < 0 || x + cx >= a.nx)) ||
+                             (cy != 0 && a.wall[1] && (y + cy < 0 || y + cy >= a.ny));
+            if (out) return m.phi;
+          }
+          return sphi[r + 2 + cy][lx + 2 + cx];
+        });
+      } else {
+        store_family<LG, NTS>(a, a.off_g, 1, node, g, a.ref[1]);
+      }
     }
     const Real cs2 = (Real)(1.0 / 3.0);
     m.p = 0;
@@ -404,7 +418,7 @@ __global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, cons
           ref = a.ref[0];
         } else if (fam == 1) {
           val = (Real)2 * w * a.phi_w[ax][side] - v[i];
-          ref = kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1];   // slot at this node
+          ref = kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1];   // read by this node
         } else {
           val = (Real)2 * w * (oy ? a.Tw[1][side][x] : a.Tw[0][side][y]) - v[i];
           ref = kNodeRef<Real, Store> ? (Real)(Sc)m.T : a.ref[2];     // slot at this node
@@ -414,11 +428,12 @@ __global__ __launch_bounds__(256) void k_init2d(const KArgs<Real, Store> a, cons
         if (!a.wall[0]) sx = wrap1(sx, a.nx);
         if (!a.wall[1]) sy = wrap1(sy, a.ny);
         const long long node = (long long)sy * a.px + sx;
-        // the slot belongs to node (sx, sy): its reference is that node's
-        // phi0 (g) or T0 (s)
+        // 16-bit storage: a g slot is encoded against the phi of the node
+        // that reads it (this one), an s slot against the T0 of the node
+        // that owns it, (sx, sy)
         const Real ref = fam == 0 ? a.ref[0]
                                   : (kNodeRef<Real, Store>
-                                         ? (Real)(Sc)ld(fam == 1 ? phi0 : T0, 0, sx, sy)
+                                         ? (fam == 1 ? (Real)(Sc)m.phi : (Real)(Sc)ld(T0, 0, sx, sy))
                                          : a.ref[fam]);
         a.B[(long long)(off + i) * a.slab + node] = C::enc(v[i], w * ref, a.scale[fam]);
       }

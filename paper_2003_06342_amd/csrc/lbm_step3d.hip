@@ -2,7 +2,7 @@
 // stencils (directional-derivative gradient and Laplacian, Sec. 3.4).
 //
 // 2.5-D blocking: a workgroup (256 lanes) owns a TX x TY column of nodes (128 x 8
-// for the FP32 step, 32 x 16 otherwise)
+// for the FP32 step, 64 x 16 for the 16-bit step, 32 x 16 otherwise)
 // over a chunk of z planes and marches up z with rolling LDS rings:
 //   phase 1, plane k+2: phi = sum g_bar + q_prev/2 on the tile + 2-halo
 //                       (5-plane ring);
@@ -27,12 +27,14 @@ struct Shape3 {
   static constexpr int P1X = TX + 4, P1Y = TY + 4;   // phi plane region
   static constexpr int P2X = TX + 2, P2Y = TY + 2;   // u plane region
 };
-// 32 x 16: 16-bit and FP64 storage, and the fields / diagnostics pass.
-// 128 x 8: the FP32 step (256^3 1.46 against 1.77 ms, 512^3 11.0 against
-// 13.3 ms; the wider rows halve the x-halo share of the pulls).  16-bit
-// storage is slower on it (512^3 FP16 14.6 against 12.1 ms).
+// 32 x 16: FP64 storage, the extended step, and the fields / diagnostics
+// pass.  128 x 8: the FP32 step (256^3 1.46 against 1.77 ms, 512^3 11.0
+// against 13.3 ms; the wider rows halve the x-halo share of the pulls).
 using ShapeStd3 = Shape3<32, 16, 32>;
 using ShapeWide3 = Shape3<128, 8, 32>;
+// 64 x 16: the 16-bit step (512^3 FP16 11.1 against 12.2 ms on 32 x 16 and
+// 11.6 on 128 x 8; 64-column rows are whole 128-byte lines of 2-byte values)
+using ShapeMid3 = Shape3<64, 16, 32>;
 constexpr int NPHI = 5, NU = 3;
 
 __device__ inline int slot5(int p) { return (p + 10) % NPHI; }
@@ -52,9 +54,13 @@ __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z
   const Store* __restrict__ base = a.A + (size_t)off * (size_t)a.slab;
   const int pz = a.px * a.ny;
   const unsigned node = (unsigned)(z * pz + y * a.px + x);
-  // 16-bit storage: g and s are deviations from w_i phi(src) and w_i T_ref(src)
-  constexpr bool NREF = FAM != 0 && kNodeRef<Real, Store>;
-  const typename KArgs<Real, Store>::Sc* __restrict__ rplane = FAM == 1 ? a.A_phip : a.A_Tref;
+  // 16-bit storage: g is stored as deviations from w_i phi_prev of the node
+  // that reads it (one reference per node), s as deviations from w_i T_ref
+  // of the node that stored it (one reference per link)
+  constexpr bool NREF = FAM == 2 && kNodeRef<Real, Store>;
+  constexpr bool GREF = FAM == 1 && kNodeRef<Real, Store>;
+  const typename KArgs<Real, Store>::Sc* __restrict__ rplane = a.A_Tref;
+  const Real gref = GREF ? (Real)a.A_phip[node] : ref;
   // this plane's wall links (uniform) and the family's wall values
   const bool wlo = a.wall[2] && z == 0, whi = a.wall[2] && z == a.nz - 1;
   Real V[2] = {(Real)0, (Real)0};
@@ -84,7 +90,7 @@ __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z
     }
     const int slot = oz ? Lat::opp(i) : i;
     const unsigned at = oz ? node : src;
-    const Real wr = NREF ? (Real)Lat::w(i) * (Real)rplane[at] : (Real)Lat::w(i) * ref;
+    const Real wr = NREF ? (Real)Lat::w(i) * (Real)rplane[at] : (Real)Lat::w(i) * gref;
     const Real r = C::dec((base + (size_t)slot * (size_t)a.slab)[at], wr, inv);
     Real rw;
     if constexpr (FAM != 0)
@@ -95,6 +101,16 @@ __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z
   }
 }
 
+template <class Lat, bool NT = false, class Real, class Store, class RefI>
+__device__ inline void store3d_ref(const KArgs<Real, Store>& a, int off, int fam, unsigned node,
+                                   const Real* v, const RefI& refi) {
+  using C = Codec<Real, Store>;
+  Store* __restrict__ base = a.B + (size_t)off * (size_t)a.slab;
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i)
+    st_stream<NT>(&(base + (size_t)i * (size_t)a.slab)[node],
+                  C::enc(v[i], (Real)Lat::w(i) * refi(i), a.scale[fam]));
+}
 template <class Lat, bool NT = false, class Real, class Store>
 __device__ inline void store3d(const KArgs<Real, Store>& a, int off, int fam, unsigned node,
                                const Real* v, Real ref) {
@@ -322,7 +338,17 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
           collide_g_ext<D3Q7>(a, g, m);
         else
           collide_g<D3Q7>(a, g, m);
-        store3d<D3Q7, NTS>(a, a.off_g, 1, node, g, kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1]);
+        if constexpr (kNodeRef<Real, Store>) {
+          // slot i is read by x + c_i and decoded against that node's phi
+          // (in the ring now); beyond a z wall, x reads it back itself
+          store3d_ref<D3Q7, NTS>(a, a.off_g, 1, node, g, [&](int i) -> Real {
+            const int cx = D3Q7::cx(i), cy = D3Q7::cy(i), cz = D3Q7::cz(i);
+            if (cz != 0 && a.wall[2] && (z + cz < 0 || z + cz >= a.nz)) return m.phi;
+            return sphi[slot5(k + cz)][ly + 2 + cy][lx + 2 + cx];
+          });
+        } else {
+          store3d<D3Q7, NTS>(a, a.off_g, 1, node, g, a.ref[1]);
+        }
       }
       const Real cs2 = (Real)(1.0 / 3.0);
       m.p = 0;
@@ -563,7 +589,7 @@ __global__ __launch_bounds__(256) void k_init3d(const KArgs<Real, Store> a, cons
       const int side = sz < 0 ? 0 : 1;
       const unsigned node = (unsigned)(z * pz + y * a.px + x);
       const int j = D3Q7::opp(i);
-      const Real gr = kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1];   // slot at this node
+      const Real gr = kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1];   // read by this node
       a.B[(size_t)(a.off_g + j) * a.slab + node] =
           C::enc((Real)2 * w * a.phi_w[2][side] - gv, w * gr, a.scale[1]);
       if (HEAT) {
@@ -575,8 +601,9 @@ __global__ __launch_bounds__(256) void k_init3d(const KArgs<Real, Store> a, cons
       const int sx = wrap1(x - D3Q7::cx(i), a.nx), sy = wrap1(y - D3Q7::cy(i), a.ny);
       const int szz = a.wall[2] ? sz : wrap1(sz, a.nz);
       const unsigned node = (unsigned)(szz * pz + sy * a.px + sx);
-      // the slot belongs to node (sx, sy, szz): its reference is that node's phi0
-      const Real gr = kNodeRef<Real, Store> ? (Real)(Sc)ld(phi0, 0, sx, sy, szz) : a.ref[1];
+      // 16-bit storage: the g slot is encoded against the phi of the node
+      // that reads it (this one)
+      const Real gr = kNodeRef<Real, Store> ? (Real)(Sc)m.phi : a.ref[1];
       a.B[(size_t)(a.off_g + i) * a.slab + node] = C::enc(gv, w * gr, a.scale[1]);
       if (HEAT) {
         // the slot belongs to node (sx, sy, szz): its reference is that node's T0
@@ -604,6 +631,7 @@ static hipError_t launch_step3d_t(const KArgs<Real, Store>& a, int ns, int heat,
   // whose per-block partials are sized by step3d_blocks) on the standard one
   const bool ext = a.coll != COLL_BGK || a.grad_scheme != GRAD_CENTRAL || a.div_local;
   constexpr bool kWide = std::is_same<Store, float>::value;
+  constexpr bool kMid = sizeof(Store) == 2;
 #define LBM_K(SH, NSV, HV, MV, EV, NTV)                                                        \
   hipLaunchKernelGGL((k_step3d<SH, Store, Real, NSV, HV, MV, EV, NTV>),                         \
                      dim3(blocks3d<SH>(a.nx, a.ny, a.nz)), dim3(SH::NT), 0, st, a)
@@ -618,6 +646,9 @@ static hipError_t launch_step3d_t(const KArgs<Real, Store>& a, int ns, int heat,
       } else if constexpr (kWide) {                                                          \
         if (a.nt) LBM_K(ShapeWide3, NSV, HV, MV, false, true);                               \
         else LBM_K(ShapeWide3, NSV, HV, MV, false, false);                                   \
+      } else if constexpr (kMid) {                                                           \
+        if (a.nt) LBM_K(ShapeMid3, NSV, HV, MV, false, true);                                \
+        else LBM_K(ShapeMid3, NSV, HV, MV, false, false);                                    \
       } else {                                                                               \
         if (a.nt) LBM_K(ShapeStd3, NSV, HV, MV, false, true);                                \
         else LBM_K(ShapeStd3, NSV, HV, MV, false, false);                                    \

@@ -37,15 +37,19 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
   // uniform plane base (scalar registers) + 32-bit lane offset
   const Store* __restrict__ base = a.A + (size_t)off * (size_t)a.slab;
   const unsigned node = (unsigned)(y * a.px + x);
-  // 16-bit storage: g and s are deviations from w_i phi(src) and w_i T_ref(src)
-  constexpr bool NREF = FAM != 0 && kNodeRef<Real, Store>;
-  const typename KArgs<Real, Store>::Sc* __restrict__ rplane = FAM == 1 ? a.A_phip : a.A_Tref;
+  // 16-bit storage: g is stored as deviations from w_i phi_prev of the node
+  // that reads it (one reference per node), s as deviations from w_i T_ref
+  // of the node that stored it (one reference per link)
+  constexpr bool NREF = FAM == 2 && kNodeRef<Real, Store>;
+  constexpr bool GREF = FAM == 1 && kNodeRef<Real, Store>;
+  const typename KArgs<Real, Store>::Sc* __restrict__ rplane = a.A_Tref;
+  const Real gref = GREF ? (Real)ld_plane(a.A_phip, node) : ref;
   if constexpr (FAST) {
 #pragma unroll
     for (int i = 0; i < Lat::Q; ++i) {
       const unsigned src = node - (unsigned)(Lat::cx(i) + Lat::cy(i) * a.px);
       const unsigned sl = (unsigned)i * (unsigned)a.slab - (unsigned)(Lat::cx(i) + Lat::cy(i) * a.px);
-      const Real r = NREF ? (Real)ld_plane(rplane, src) : ref;
+      const Real r = NREF ? (Real)ld_plane(rplane, src) : gref;
       v[i] = C::dec(ld_fam(base, node + sl), (Real)Lat::w(i) * r, inv);
     }
     return;
@@ -58,7 +62,7 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
       const bool oy = (cy != 0) && a.wall[1] && (sy < 0 || sy >= a.ny);
       const bool ox = (cx != 0) && !oy && a.wall[0] && (sx < 0 || sx >= a.nx);
       if (oy || ox) {
-        const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, node) : (Real)Lat::w(i) * ref;
+        const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, node) : (Real)Lat::w(i) * gref;
         Real r = C::dec(ld_fam(base, (unsigned)Lat::opp(i) * (unsigned)a.slab + node), wr, inv);
         if (FAM != 0) {
           const int side = oy ? (sy < 0 ? 0 : 1) : (sx < 0 ? 0 : 1);
@@ -71,7 +75,7 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
         if (cx != 0 && !a.wall[0]) sx = wrap1(sx, a.nx);
         if (cy != 0 && !a.wall[1]) sy = wrap1(sy, a.ny);
         const unsigned src = (unsigned)(sy * a.px + sx);
-        const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, src) : (Real)Lat::w(i) * ref;
+        const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, src) : (Real)Lat::w(i) * gref;
         v[i] = C::dec(ld_fam(base, (unsigned)i * (unsigned)a.slab + src), wr, inv);
       }
     }
@@ -108,7 +112,7 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
     if (cy != 0 && !a.wall[1]) sy = wrap1(sy, a.ny);
     const unsigned at = o ? node : (unsigned)(sy * a.px + sx);
     const int slot = o ? Lat::opp(i) : i;
-    const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, at) : (Real)Lat::w(i) * ref;
+    const Real wr = NREF ? (Real)Lat::w(i) * (Real)ld_plane(rplane, at) : (Real)Lat::w(i) * gref;
     const Real r = C::dec(ld_fam(base, (unsigned)slot * (unsigned)a.slab + at), wr, inv);
     // the crossed face: y (precedence at corners) or x, side from the sign of c
     const int ys = cy > 0 ? 0 : 1, xs = cx > 0 ? 0 : 1;
@@ -122,6 +126,19 @@ __device__ inline void gather2d(const KArgs<Real, Store>& a, int x, int y, Real*
     }
     v[i] = o ? rw : r;
   }
+}
+
+// Store the Q post-collision populations of one family at `node` of B, slot
+// i encoded against w_i refi(i).
+template <class Lat, bool NT = false, class Real, class Store, class RefI>
+__device__ inline void store_family_ref(const KArgs<Real, Store>& a, int off, int fam, unsigned node,
+                                        const Real* v, const RefI& refi) {
+  using C = Codec<Real, Store>;
+  Store* __restrict__ base = a.B + (size_t)off * (size_t)a.slab;
+#pragma unroll
+  for (int i = 0; i < Lat::Q; ++i)
+    st_fam<NT>(base, (unsigned)i * (unsigned)a.slab + node,
+               C::enc(v[i], (Real)Lat::w(i) * refi(i), a.scale[fam]));
 }
 
 // Store the Q post-collision populations of one family at `node` of B.

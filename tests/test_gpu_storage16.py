@@ -1,10 +1,10 @@
 """16-bit deviation storage (FP16 / BF16, FP32 arithmetic) against the FP64
-oracle.  f is stored as (v - w_i ref_f) * 2^k with a global reference; g and
-s as deviations from w_i phi(x) and w_i T(x) of the node x that stored the
-population (per-node references, the lagged phi plane and a T_ref plane).
+oracle.  f is stored as (v - w_i ref_f) * 2^k with a global reference; g as
+deviations from w_i phi of the node that reads the slot (its lagged phi), s
+as deviations from w_i T(x) of the node x that stored it (a T_ref plane).
 
 Measured (relative L2 after 100 steps in 2-D, 40 in 3-D): FP16 phi 7e-6 /
-1.5e-5, T 7e-5 / 7e-5, |u| 5e-4 / 4e-4, p 1.0e-3 / 4e-4 (2-D / 3-D).  The
+5e-6, T 7e-5 / 1.3e-4, |u| 3.5e-4 / 4e-4, p 7.6e-4 / 5e-4 (2-D / 3-D).  The
 per-node references took T from 5e-3 and phi from 5e-4.  BF16 is about 8x
 worse (3 fewer mantissa bits).
 
@@ -55,6 +55,27 @@ def test_deviation_storage(storage, case, steps):
         assert e16[k] <= bar, (k, e16)
     # the compressed path is never better than FP32 storage
     assert e16["phi"] >= e32["phi"]
+
+
+@pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
+def test_film3d_16bit_step_tiles_interior(storage):
+    """The 16-bit 3-D step's 64 x 16 tiles with interior (seam-free) tiles in
+    x and y and ragged last tiles: 200 x 56 x 20, 40 steps, same bars as the
+    film3d case above."""
+    need_gpu()
+    prm = I.film3d_params(200, nz=20, wavelength=100.0)
+    prm["ny"] = 56
+    prm["gravity"] = [0.0, 0.0, -5e-5]
+    phi0, T0 = I.film3d_fields(prm, seed=3, h0=6.0, amp=1.5, wavelength=100.0)
+    steps = 40
+    say(f"[storage16] film3d 200x56x20 {storage} steps={steps}")
+    ref = oracle_run(prm, phi0, T0, steps)
+    e16 = compare(gpu_run(prm, phi0, T0, steps, storage), ref)
+    say(f"[storage16] film3d 200x56x20 {storage}: {e16}")
+    bars = ({"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 3e-3} if storage == "f16dev" else
+            {"phi": 1e-3, "T": 5e-3, "umag": 2e-2, "p": 5e-2})
+    for k, bar in bars.items():
+        assert e16[k] <= bar, (k, e16)
 
 
 def test_compressed_storage_64cubed_instance_of_512cubed_run():
