@@ -59,10 +59,11 @@ enum { LBM_D2Q9 = 9, LBM_D2Q5 = 5, LBM_D3Q7 = 7, LBM_D3Q19 = 19 };
 
 /* Population storage.  F16_DEV / BF16_DEV store each population as the
  * 16-bit float (value - w_i * ref) * 2^k with a power-of-two scale;
- * arithmetic is FP32.  ref is a per-family constant for f and g.  For the
- * temperature family s it is per node: T_ref(x), the temperature of the node
- * x that stored the population, kept as one more FP32 plane of the state.
- * Lagged scalars stay FP32. */
+ * arithmetic is FP32.  ref is a constant for f; for the phase-field family g
+ * it is the lagged phi of the node that reads the population; for the
+ * temperature family s it is T_ref(x), the temperature of the node x that
+ * stored the population, kept as one more FP32 plane of the state.  Lagged
+ * scalars stay FP32. */
 enum { LBM_ST_F64 = 0, LBM_ST_F32 = 1, LBM_ST_F16_DEV = 2, LBM_ST_BF16_DEV = 3 };
 
 /* Per-axis boundary: periodic, or half-way walls on both faces.  A wall is
