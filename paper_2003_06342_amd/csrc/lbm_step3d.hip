@@ -32,9 +32,11 @@ struct Shape3 {
 // against 13.3 ms; the wider rows halve the x-halo share of the pulls).
 using ShapeStd3 = Shape3<32, 16, 32>;
 using ShapeWide3 = Shape3<128, 8, 32>;
-// 64 x 16: the 16-bit step (512^3 FP16 11.1 against 12.2 ms on 32 x 16 and
-// 11.6 on 128 x 8; 64-column rows are whole 128-byte lines of 2-byte values)
-using ShapeMid3 = Shape3<64, 16, 32>;
+// 64 x 16 over 16-plane chunks: the 16-bit step (512^3 FP16 11.1 against
+// 12.2 ms on 32 x 16 and 11.6 on 128 x 8 with 32-plane chunks; 64-column rows
+// are whole 128-byte lines of 2-byte values; 16-plane chunks 10.77 against
+// 10.92 ms with 32 and 11.08 with 8)
+using ShapeMid3 = Shape3<64, 16, 16>;
 constexpr int NPHI = 5, NU = 3;
 
 __device__ inline int slot5(int p) { return (p + 10) % NPHI; }
@@ -101,6 +103,16 @@ __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z
   }
 }
 
+// Output store of the 3-D step: non-temporal (NT) also for 2-byte
+// populations, which gain here (512^3 FP16 11.10 -> 10.92 ms), unlike the
+// 2-D step's 4-row tiles.
+template <bool NT, class T>
+__device__ __forceinline__ void st_stream3(T* p, T v) {
+  if constexpr (NT && sizeof(T) == 2)
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), (unsigned short*)p);
+  else
+    st_stream<NT>(p, v);
+}
 template <class Lat, bool NT = false, class Real, class Store, class RefI>
 __device__ inline void store3d_ref(const KArgs<Real, Store>& a, int off, int fam, unsigned node,
                                    const Real* v, const RefI& refi) {
@@ -108,8 +120,8 @@ __device__ inline void store3d_ref(const KArgs<Real, Store>& a, int off, int fam
   Store* __restrict__ base = a.B + (size_t)off * (size_t)a.slab;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i)
-    st_stream<NT>(&(base + (size_t)i * (size_t)a.slab)[node],
-                  C::enc(v[i], (Real)Lat::w(i) * refi(i), a.scale[fam]));
+    st_stream3<NT>(&(base + (size_t)i * (size_t)a.slab)[node],
+                   C::enc(v[i], (Real)Lat::w(i) * refi(i), a.scale[fam]));
 }
 template <class Lat, bool NT = false, class Real, class Store>
 __device__ inline void store3d(const KArgs<Real, Store>& a, int off, int fam, unsigned node,
@@ -118,7 +130,7 @@ __device__ inline void store3d(const KArgs<Real, Store>& a, int off, int fam, un
   Store* __restrict__ base = a.B + (size_t)off * (size_t)a.slab;
 #pragma unroll
   for (int i = 0; i < Lat::Q; ++i)
-    st_stream<NT>(&(base + (size_t)i * (size_t)a.slab)[node], C::enc(v[i], (Real)Lat::w(i) * ref, a.scale[fam]));
+    st_stream3<NT>(&(base + (size_t)i * (size_t)a.slab)[node], C::enc(v[i], (Real)Lat::w(i) * ref, a.scale[fam]));
 }
 
 // D3Q19 directional-derivative gradient and Laplacian from the phi ring
