@@ -120,3 +120,52 @@ def test_film3d_full_size_256_bench_configuration():
         say(f"[parity3d] full size {storage}: {errs}")
         for k in ("phi", "T", "umag", "p"):
             assert errs[k] <= tol, (storage, k, errs)
+
+
+def test_film3d_512_compressed_workload_windows():
+    """The 512^3 compressed-storage workload itself (seed 5, z = 64 + 6 cos
+    cos + noise) in the launch configurations bench.py times (FP16 and BF16
+    on 64 x 16 x 16 tiles, FP32 on 128 x 8 x 32, FP64 on 32 x 16 x 32): 2 steps
+    of the full grid against the oracle run on 40 x 40 column windows over
+    the whole height (x and y wrapped at the window's edges), compared more
+    than 11 nodes (two steps' reach) inside them; three windows, one across
+    both periodic seams.  FP64 within 1e-10, FP32 within 1e-5, FP16 within
+    1e-3 and BF16 within 1e-2."""
+    import torch
+    from paper_2003_06342_amd import lbm
+    from oracle.lbm_oracle import Model
+    need_gpu()
+    prm = I.film3d_params(512)
+    phi0, T0 = I.film3d_fields(prm, seed=5, h0=64.0, amp=6.0)
+    n, W, m = 2, 40, 11
+    origins = ((500, 500), (100, 300), (256, 64))
+    idx = lambda o: (o + np.arange(W)) % 512
+    keys = ("phi", "T", "ux", "uy", "uz", "p")
+    refs = {}
+    for (y0, x0) in origins:
+        pw = dict(prm, nx=W, ny=W)
+        M = Model(pw)
+        sub = lambda a: a[:, idx(y0)][:, :, idx(x0)]
+        st = M.run(M.init(sub(phi0), sub(T0)), n)
+        f = M.fields(st)
+        refs[(y0, x0)] = {k: f[k].numpy()[:, m:W - m, m:W - m] for k in keys}
+    for storage, tol in (("f64", 1e-10), ("f32", 1e-5), ("f16dev", 1e-3), ("bf16dev", 1e-2)):
+        say(f"[parity3d] 512^3 {storage}: {n} steps, windows {origins}")
+        sim = lbm.Sim(prm, storage)
+        sim.init(phi0, T0)
+        sim.step(n)
+        f = sim.fields()
+        worst = {}
+        for (y0, x0) in origins:
+            ys = torch.tensor(idx(y0)[m:W - m], device=f["phi"].device)
+            xs = torch.tensor(idx(x0)[m:W - m], device=f["phi"].device)
+            g = {k: f[k].index_select(1, ys).index_select(2, xs).double().cpu().numpy() for k in keys}
+            for k, e in compare(g, refs[(y0, x0)]).items():
+                worst[k] = max(worst.get(k, 0.0), e)
+        sim.sync()
+        sim.close()
+        del f
+        torch.cuda.empty_cache()
+        say(f"[parity3d] 512^3 {storage}: worst window errors {worst}")
+        for k in ("phi", "T", "umag", "p"):
+            assert worst[k] <= tol, (storage, k, worst)
