@@ -48,7 +48,8 @@ __device__ inline int slot3(int p) { return (p + 9) % NU; }
 // crosses a z wall (c_z = +1 at z = 0, c_z = -1 at z = nz - 1) reads the
 // opposite slot of the node itself; slot and transform are selected, not
 // branched on, so the loads of all Q links issue back to back.
-template <class Lat, int FAM, bool XYIN, class Real, class Store>
+// NTL: non-temporal loads (the last read of these populations this step).
+template <class Lat, int FAM, bool XYIN, bool NTL = false, class Real, class Store>
 __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z, Real* v) {
   using C = Codec<Real, Store>;
   const int off = FAM == 0 ? a.off_f : (FAM == 1 ? a.off_g : a.off_s);
@@ -93,7 +94,15 @@ __device__ inline void gather3d(const KArgs<Real, Store>& a, int x, int y, int z
     const int slot = oz ? Lat::opp(i) : i;
     const unsigned at = oz ? node : src;
     const Real wr = NREF ? (Real)Lat::w(i) * (Real)rplane[at] : (Real)Lat::w(i) * gref;
-    const Real r = C::dec((base + (size_t)slot * (size_t)a.slab)[at], wr, inv);
+    const Store* sp = &(base + (size_t)slot * (size_t)a.slab)[at];
+    Store raw;
+    if constexpr (NTL && sizeof(Store) == 2)
+      raw = __builtin_bit_cast(Store, __builtin_nontemporal_load((const unsigned short*)sp));
+    else if constexpr (NTL)
+      raw = __builtin_nontemporal_load(sp);
+    else
+      raw = *sp;
+    const Real r = C::dec(raw, wr, inv);
     Real rw;
     if constexpr (FAM != 0)
       rw = -r + (Real)2 * (Real)Lat::w(i) * V[side];
@@ -295,7 +304,7 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
 #pragma unroll
         for (int d = 0; d < 3; ++d) m.u[d] = su[slot3(k)][d][ly + 1][lx + 1];
       } else if constexpr (NS) {
-        gather3d<D3Q19, 0, XYIN>(a, x, y, z, f);
+        gather3d<D3Q19, 0, XYIN, true>(a, x, y, z, f);   // read once (no phase 2)
         Real mm[3] = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
@@ -316,7 +325,7 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
       m.q = 0;
       if constexpr (HEAT) {
         Real s[7];
-        gather3d<D3Q7, 2, XYIN>(a, x, y, z, s);
+        gather3d<D3Q7, 2, XYIN, true>(a, x, y, z, s);   // s is read once per step
         if constexpr (NS) {
           if constexpr (EXT || MODE == MODE_MACRO) {
             if (a.div_local)
@@ -345,7 +354,7 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
       }
       if constexpr (MODE == MODE_STEP) {
         Real g[7];
-        gather3d<D3Q7, 1, XYIN>(a, x, y, z, g);
+        gather3d<D3Q7, 1, XYIN, true>(a, x, y, z, g);   // the last read of g this step
         if constexpr (EXT)
           collide_g_ext<D3Q7>(a, g, m);
         else
@@ -366,7 +375,7 @@ __device__ __forceinline__ void march3d(const KArgs<Real, Store>& a, Real (*sphi
       m.p = 0;
       if constexpr (NS) {
         if constexpr (HEAT) {
-          gather3d<D3Q19, 0, XYIN>(a, x, y, z, f);
+          gather3d<D3Q19, 0, XYIN, true>(a, x, y, z, f);   // the last read of f this step
 #pragma unroll
           for (int i = 0; i < 19; ++i) m0f += f[i];
         }
