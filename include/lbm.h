@@ -245,8 +245,11 @@ lbm_status lbm_sync(lbm_ctx* ctx);
 
 /* Checkpointing policy of the tape.  SQRT: snapshots every K = ceil(sqrt(N))
  * steps plus one recomputed segment of K states (memory O(sqrt N) states,
- * N - ceil(N/K) recomputed steps).  BINOMIAL is reserved (returns
- * LBM_E_UNSUPPORTED). */
+ * N - ceil(N/K) recomputed steps).  BINOMIAL: binomial checkpointing
+ * (Griewank and Walther): s checkpoints, the fewest with C(s + 3, 3) >= N,
+ * plus two work states, so that no step is recomputed more than three
+ * times (N = 2000: 23 states against 90, about 1.9 N recomputed steps
+ * against 0.98 N).  Both give the same gradients bit for bit. */
 enum { LBM_TAPE_SQRT = 0, LBM_TAPE_BINOMIAL = 1 };
 
 /* Bytes of the tape for nsteps under `policy`. */

@@ -13,10 +13,12 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/lbm.h"
 #include "lbm_kernels.h"
 #include "lbm_adjargs.h"
+#include "lbm_tape.h"
 
 using namespace lbm;
 
@@ -76,6 +78,7 @@ struct lbm_ctx {
   char* tape;
   size_t tape_bytes;
   int64_t tape_n, tape_k, tape_nsnap, tape_end_step;
+  int32_t tape_policy;
   int tape_ready;
   // the current state is step `step` of an lbm_init_fields call with u0 ==
   // NULL (the initialisation the reverse sweep differentiates)
@@ -752,24 +755,59 @@ lbm_status backward_t(lbm_ctx* c, const void* gphi, const void* gT, int32_t gdt,
     std::swap(b.lA, b.lP);   // the seed left lambda_A of X^N in lP
   }
   const int64_t N = c->tape_n, K = c->tape_k;
-  for (int64_t s = c->tape_nsnap - 1; s >= 0; --s) {
-    const int64_t n0 = s * K, n1 = std::min<int64_t>(n0 + K, N);
-    e = hipMemcpyAsync(seg, snaps + (size_t)s * ss, ss, hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return hip_check(e, "tape restore");
-    for (int64_t k = 0; k + 1 < n1 - n0; ++k) {   // recompute the segment's states
-      KArgs<Real, Real> a = make_args_blobs<Real, Real>(c, seg + (size_t)k * ss, seg + (size_t)(k + 1) * ss);
-      e = launch_step2d(a, c->ns, c->heat, MODE_STEP, c->stream);
-      if (e != hipSuccess) return hip_check(e, "segment recompute");
+  auto adj_step = [&](const char* state) -> hipError_t {
+    KArgs<Real, Real> a = make_args_blobs<Real, Real>(c, state, nullptr);
+    hipError_t er = launch_adj_step2d(a, b, c->stream);
+    std::swap(b.lA, b.lP);   // the step left lambda_A of its input state in lP
+    return er;
+  };
+  if (c->tape_policy == LBM_TAPE_SQRT) {
+    for (int64_t s = c->tape_nsnap - 1; s >= 0; --s) {
+      const int64_t n0 = s * K, n1 = std::min<int64_t>(n0 + K, N);
+      e = hipMemcpyAsync(seg, snaps + (size_t)s * ss, ss, hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) return hip_check(e, "tape restore");
+      for (int64_t k = 0; k + 1 < n1 - n0; ++k) {   // recompute the segment's states
+        KArgs<Real, Real> a = make_args_blobs<Real, Real>(c, seg + (size_t)k * ss, seg + (size_t)(k + 1) * ss);
+        e = launch_step2d(a, c->ns, c->heat, MODE_STEP, c->stream);
+        if (e != hipSuccess) return hip_check(e, "segment recompute");
+      }
+      for (int64_t k = n1 - n0 - 1; k >= 0; --k) {
+        e = adj_step(seg + (size_t)k * ss);
+        if (e != hipSuccess) return hip_check(e, "adjoint step");
+      }
     }
-    for (int64_t k = n1 - n0 - 1; k >= 0; --k) {
-      KArgs<Real, Real> a = make_args_blobs<Real, Real>(c, seg + (size_t)k * ss, nullptr);
-      e = launch_adj_step2d(a, b, c->stream);
-      if (e != hipSuccess) return hip_check(e, "adjoint step");
-      std::swap(b.lA, b.lP);   // the step left lambda_A of state k in lP
-    }
+  } else {
+    // slots 0 .. nsnap-1 hold checkpoints (slot 0: X^0); two work states follow
+    char* w[2] = {snaps + (size_t)c->tape_nsnap * ss, snaps + (size_t)(c->tape_nsnap + 1) * ss};
+    hipError_t er = hipSuccess;
+    // X of `slot` advanced by `steps` steps (ping-pong through the work states)
+    auto advance = [&](int64_t slot, int64_t steps) -> const char* {
+      const char* cur = snaps + (size_t)slot * ss;
+      for (int64_t k = 0; k < steps && er == hipSuccess; ++k) {
+        char* out = w[k & 1];
+        KArgs<Real, Real> a = make_args_blobs<Real, Real>(c, cur, out);
+        er = launch_step2d(a, c->ns, c->heat, MODE_STEP, c->stream);
+        cur = out;
+      }
+      return cur;
+    };
+    auto adj = [&](int64_t slot, int64_t k) -> bool {
+      const char* x = advance(slot, k);
+      if (er == hipSuccess) er = adj_step(x);
+      return er == hipSuccess;
+    };
+    auto store = [&](int64_t slot, int64_t j, int64_t to) -> bool {
+      const char* x = advance(slot, j);
+      if (er == hipSuccess)
+        er = hipMemcpyAsync(snaps + (size_t)to * ss, x, ss, hipMemcpyDeviceToDevice, c->stream);
+      return er == hipSuccess;
+    };
+    binom_reverse(0, N, c->tape_nsnap - 1, 0, true, adj, store);
+    if (er != hipSuccess) return hip_check(er, "binomial reverse sweep");
   }
-  {  // initial condition (segment 0's first state is X^0)
-    KArgs<Real, Real> a = make_args_blobs<Real, Real>(c, seg, nullptr);
+  {  // initial condition: X^0 (the first slot of the last segment restored, or slot 0)
+    const char* x0 = c->tape_policy == LBM_TAPE_SQRT ? seg : snaps;
+    KArgs<Real, Real> a = make_args_blobs<Real, Real>(c, x0, nullptr);
     e = launch_adj_init2d(a, b, dphi, dT0, c->stream);
     if (e != hipSuccess) return hip_check(e, "adjoint init");
   }
@@ -797,7 +835,10 @@ extern "C" {
 lbm_status lbm_tape_size(const lbm_ctx* c, int64_t nsteps, int32_t policy, size_t* bytes) {
   if (!c || !bytes) return fail(LBM_E_INVAL, "NULL argument");
   if (nsteps < 1) return fail(LBM_E_INVAL, "nsteps must be >= 1");
-  if (policy == LBM_TAPE_BINOMIAL) return fail(LBM_E_UNSUPPORTED, "LBM_TAPE_BINOMIAL is not built");
+  if (policy == LBM_TAPE_BINOMIAL) {
+    *bytes = (size_t)(binom_slots(nsteps) + 2) * state_bytes(c);
+    return LBM_OK;
+  }
   if (policy != LBM_TAPE_SQRT) return fail(LBM_E_INVAL, "unknown tape policy %d", policy);
   int64_t k, ns;
   tape_shape(nsteps, k, ns);
@@ -820,7 +861,12 @@ lbm_status lbm_forward_taped(lbm_ctx* c, int64_t nsteps, int32_t policy, void* t
   if (bytes < need) return fail(LBM_E_NOMEM, "tape has %zu bytes, needs %zu", bytes, need);
   if (((uintptr_t)tape & 255) != 0) return fail(LBM_E_INVAL, "tape must be 256-byte aligned");
   int64_t k, ns;
-  tape_shape(nsteps, k, ns);
+  if (policy == LBM_TAPE_SQRT) {
+    tape_shape(nsteps, k, ns);
+  } else {   // binomial: k unused, ns checkpoint slots
+    k = 0;
+    ns = binom_slots(nsteps);
+  }
   const size_t ss = state_bytes(c);
   char* t = (char*)tape;
   auto snap = [&](int64_t s) -> hipError_t {
@@ -836,12 +882,23 @@ lbm_status lbm_forward_taped(lbm_ctx* c, int64_t nsteps, int32_t policy, void* t
   c->tape_ready = 0;
   hipError_t e = snap(0);
   if (e != hipSuccess) return hip_check(e, "tape snapshot");
+  // binomial: the split states of the reverse sweep's first descent (its
+  // right spine) are stored on the way
+  std::vector<std::pair<int64_t, int64_t>> spine;
+  if (policy == LBM_TAPE_BINOMIAL)
+    binom_spine(nsteps, [&](int64_t step, int64_t slot) { spine.emplace_back(step, slot); });
+  size_t next = 0;
   for (int64_t n = 1; n <= nsteps; ++n) {
     st = lbm_step(c, 1);
     if (st != LBM_OK) return st;
-    if (n % k == 0 && n < nsteps) {
+    if (policy == LBM_TAPE_SQRT && n % k == 0 && n < nsteps) {
       e = snap(n / k);
       if (e != hipSuccess) return hip_check(e, "tape snapshot");
+    }
+    if (next < spine.size() && n == spine[next].first) {
+      e = snap(spine[next].second);
+      if (e != hipSuccess) return hip_check(e, "tape snapshot");
+      ++next;
     }
   }
   c->tape = t;
@@ -849,6 +906,7 @@ lbm_status lbm_forward_taped(lbm_ctx* c, int64_t nsteps, int32_t policy, void* t
   c->tape_n = nsteps;
   c->tape_k = k;
   c->tape_nsnap = ns;
+  c->tape_policy = policy;
   c->tape_end_step = c->step;
   c->tape_ready = 1;
   return LBM_OK;
