@@ -26,8 +26,8 @@
 
 namespace lbm {
 
-// Lanes per workgroup: one tile node per lane for the time step's 4- and
-// 16-row tiles, 512 for the 64-row tiles of the fields pass.
+// Lanes per workgroup: one tile node per lane for the time step's 4-, 8-
+// and 16-row tiles, 512 for the 64-row tiles of the fields pass.
 template <int TY>
 struct StepTile {
   static constexpr int NT = TY <= 16 ? TX2 * TY : 512;
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(StepTile<TY>::NT) void k_step2d(const KArgs<Real, S
 
 // 16-bit storage: at most 128 VGPRs (4 waves per SIMD).  The codec constants
 // and per-node references pushed the 64-row tile kernel past that (0.200 ->
-// 0.136 ms at 1024 x 2048 with the cap); the 4-row carry kernel needs 72.
+// 0.136 ms at 1024 x 2048 with the cap); the 8-row carry kernel fits under it.
 template <class Store, class Real, bool NS, bool HEAT, int MODE, int TY, bool EXT, bool NTS, class LG>
 __global__ __launch_bounds__(StepTile<TY>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_step2d_w4(
     const KArgs<Real, Store> a) {
@@ -457,14 +457,15 @@ static hipError_t launch_step2d_t(const KArgs<Real, Store>& a, int ns, int heat,
                                   hipStream_t st) {
   // MODE_MACRO always uses 64-row tiles: its per-block partials are sized by
   // step2d_blocks.  The step runs one tile node per lane: 16 rows (1024
-  // lanes) for FP32, 4 rows (256 lanes) for 16-bit and FP64 storage, whose
-  // kernels hold more registers.  Measured at 1024 x 2048: FP32 0.108 ms
-  // (0.120 with 4 rows, 0.110 with 8); FP16 0.092 (0.095 with 8, 0.143 with
-  // 16); FP64 0.204 (0.228 with 8).  At 512 x 512 FP32 0.016 ms (0.018 with
-  // 4 rows).
+  // lanes) for FP32, 8 rows (512 lanes) for 16-bit storage and 4 rows (256
+  // lanes) for FP64 storage, whose kernel holds more registers.  Measured at
+  // 1024 x 2048: FP32 0.108 ms (0.120 with 4 rows, 0.110 with 8); FP64 0.204
+  // (0.228 with 8).  FP16, with the g reference per reading node: 0.0748 ms
+  // (0.0774 with 4 rows, 0.0838 with 16), 512 x 512 0.0136 (0.0153 with 4).
+  // At 512 x 512 FP32 0.016 ms (0.018 with 4 rows).
   constexpr bool st16 = sizeof(Store) == 2;
   constexpr bool small_tiles = st16 || sizeof(Store) == 8;
-  const int ty = mode != MODE_STEP ? 64 : (small_tiles ? 4 : 16);
+  const int ty = mode != MODE_STEP ? 64 : (st16 ? 8 : (small_tiles ? 4 : 16));
   const int tiles = ((a.nx + TX2 - 1) / TX2) * ((a.ny + ty - 1) / ty);
   // D2Q5 phase-field and heat populations run the extended kernels
   const bool d2q5 = a.q_gs == 5;
@@ -487,8 +488,9 @@ static hipError_t launch_step2d_t(const KArgs<Real, Store>& a, int ns, int heat,
     else if (a.nt) LBM_K(NSV, HV, MV, TYV, false, true, D2Q9);  \
     else LBM_K(NSV, HV, MV, TYV, false, false, D2Q9);           \
   } while (0)
-#define LBM_L2(NSV, HV, MV)                \
-  if constexpr (small_tiles) LBM_L(NSV, HV, MV, 4); \
+#define LBM_L2(NSV, HV, MV)                            \
+  if constexpr (st16) LBM_L(NSV, HV, MV, 8);              \
+  else if constexpr (small_tiles) LBM_L(NSV, HV, MV, 4);  \
   else LBM_L(NSV, HV, MV, 16)
 #define LBM_M(NSV, HV)                                                \
   do {                                                                \
