@@ -107,3 +107,19 @@ def test_invariant_3d_equals_2d_d2q5_on_gpu():
     say(f"[d2q5] invariance 2-D vs oracle: {errs}")
     for k in ("phi", "T", "umag", "p"):
         assert errs[k] <= 1e-10, (k, errs)
+
+
+@pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
+def test_film2d_d2q5_16bit(storage):
+    """D2Q5 g and s with 16-bit deviation storage (g referenced per reading
+    node over the five links): within the 16-bit bars of the D2Q9 film."""
+    prm, phi0, T0 = _film()
+    need_gpu()
+    say(f"[d2q5] film2d {storage}: steps=100")
+    ref = oracle_run(prm, phi0, T0, 100)
+    errs = compare(gpu_run(prm, phi0, T0, 100, storage), ref)
+    say(f"[d2q5] film2d {storage}: errors {errs}")
+    bars = ({"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 3e-3} if storage == "f16dev" else
+            {"phi": 1e-3, "T": 5e-3, "umag": 2e-2, "p": 5e-2})
+    for k, bar in bars.items():
+        assert errs[k] <= bar, (k, errs)

@@ -93,3 +93,28 @@ def test_film3d_open_top_f64():
     prm["p_wall"] = [[0.0, 0.0], [0.0, 0.0], [0.0, 1e-4]]
     phi0, T0 = I.film3d_fields(prm, seed=1, h0=8.0, amp=1.5, wavelength=36.0)
     _check("film3d_open_top", prm, phi0, T0, 20, "f64", 1e-10)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_open_top_16bit_storage(dim):
+    """Open top with FP16-deviation storage (the open face's reflected f is
+    stored against f's global reference like every other slot): within the
+    16-bit bars of the closed film (phi 1e-4, T and |u| 1e-3, p 3e-3)."""
+    if dim == 2:
+        prm, phi0, T0 = film2d_open()
+        n = 60
+    else:
+        prm = I.film3d_params(36, nz=37)
+        prm["ny"] = 20
+        prm["gravity"] = [0.0, 0.0, -5e-5]
+        prm["f_open"] = [[False, False], [False, False], [False, True]]
+        prm["p_wall"] = [[0.0, 0.0], [0.0, 0.0], [0.0, 1e-4]]
+        phi0, T0 = I.film3d_fields(prm, seed=1, h0=8.0, amp=1.5, wavelength=36.0)
+        n = 20
+    need_gpu()
+    say(f"[open] {dim}-D open top f16dev: steps={n}")
+    ref = oracle_run(prm, phi0, T0, n)
+    errs = compare(gpu_run(prm, phi0, T0, n, "f16dev"), ref)
+    say(f"[open] {dim}-D open top f16dev: errors {errs}")
+    for k, bar in {"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 3e-3}.items():
+        assert errs[k] <= bar, (k, errs)
