@@ -10,7 +10,9 @@ Geq_Allen-Cahn_Eq, SourceTerm_AllenCahn, Seq_Temp, the BGK collision of
 Eq. LBE with the variable change, and pull streaming with bounce-back and
 anti-bounce-back links (Sec. 3.3; the y wall wins at a corner).  It is
 compared with the vectorised oracle on 6 x 5 grids over several steps, and
-a planted sign mistake in the oracle is shown to fail the comparison."""
+a planted sign mistake in the oracle is shown to fail the comparison.  The
+3-D step (D3Q19 f and stencils, D3Q7 g and s with c_s^2 = 1/4, walls on z)
+is checked the same way on a 4 x 3 x 6 film."""
 import math
 
 import numpy as np
@@ -222,3 +224,196 @@ def test_bruteforce_detects_a_planted_oracle_mistake(monkeypatch):
     o = _lists(M.step(st))
     worst = max(np.abs(np.asarray(x) - np.asarray(y)).max() for x, y in zip(b, o))
     assert worst > 1e-8
+
+
+# ---------------------------------------------------------------------------
+# 3-D: D3Q19 f and stencils, D3Q7 g and s (each population with its own c_s^2,
+# R2 and R3), walls on z.  Written over dictionaries keyed by node; lattice
+# tables built here from their definitions.
+# ---------------------------------------------------------------------------
+
+def _d3q19():
+    c = [(0, 0, 0)]
+    c += [v for a in range(3) for v in (tuple(1 if b == a else 0 for b in range(3)),
+                                         tuple(-1 if b == a else 0 for b in range(3)))]
+    c += [(sx, sy, 0) for sx in (1, -1) for sy in (1, -1)]
+    c += [(sx, 0, sz) for sx in (1, -1) for sz in (1, -1)]
+    c += [(0, sy, sz) for sy in (1, -1) for sz in (1, -1)]
+    w = [1 / 3] + [1 / 18] * 6 + [1 / 36] * 12
+    return c, w, 1.0 / 3.0
+
+
+def _d3q7():
+    c = [(0, 0, 0)] + [v for a in range(3) for v in (tuple(1 if b == a else 0 for b in range(3)),
+                                                     tuple(-1 if b == a else 0 for b in range(3)))]
+    return c, [1 / 4] + [1 / 8] * 6, 0.25
+
+
+def brute_step_3d(prm, f, g, s, phip, qp):
+    """f, g, s: dict node -> list of populations (own lattice order);
+    phip, qp: dict node -> float.  Walls on z only (x, y periodic)."""
+    nx, ny, nz = prm["nx"], prm["ny"], prm["nz"]
+    CF, WF, C2F = _d3q19()
+    CG, WG, C2G = _d3q7()
+    rl, rg = prm["rho_l"], prm["rho_g"]
+    W, sig = prm["W"], prm["sigma"]
+    K, H = 1.5 * W * sig, 12.0 * sig / W
+    M, Lcp = prm["mobility"], prm["L_over_cp"]
+    grav, body, eps = prm["gravity"], prm["body_force"], prm["eps_n"]
+    nodes = [(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx)]
+    add = lambda p, c, k=1: (p[0] + k * c[0], p[1] + k * c[1], p[2] + k * c[2])
+    phi = {p: sum(g[p]) + 0.5 * qp[p] for p in nodes}
+
+    def ghost(field, p, kind, vw):
+        x, y, z = p[0] % nx, p[1] % ny, p[2]
+        if 0 <= z < nz:
+            return field[(x, y, z)]
+        v = field[(x, y, 0 if z < 0 else nz - 1)]
+        return 2.0 * vw[0 if z < 0 else 1] - v if kind == "phi" else -v
+
+    P = lambda p: ghost(phi, p, "phi", prm["phi_wall"][2])
+    d = {}
+    for p in nodes:
+        gr = [0.0, 0.0, 0.0]
+        lap = 0.0
+        for c, w in zip(CF[1:], WF[1:]):
+            pp, pm = P(add(p, c)), P(add(p, c, -1))
+            for a in range(3):
+                gr[a] += w * c[a] * 0.5 * (pp - pm)
+            lap += w * (pp - 2.0 * phi[p] + pm)
+        gr = [v / C2F for v in gr]
+        lap /= C2F
+        ph = phi[p]
+        mu = 4.0 * H * ph * (ph - 1.0) * (ph - 0.5) - K * lap
+        rho = ph * rg + (1.0 - ph) * rl
+        F = [mu * gr[a] + (rho - rl) * grav[a] + body[a] for a in range(3)]
+        m = [sum(fi * c[a] for fi, c in zip(f[p], CF)) for a in range(3)]
+        u = [(m[a] / C2F + 0.5 * F[a]) / rho for a in range(3)]
+        nrm = math.sqrt(sum(v * v for v in gr) + eps * eps)
+        d[p] = dict(gr=gr, lap=lap, mu=mu, rho=rho, F=F, u=u, n=[v / nrm for v in gr])
+    U = lambda p, a: ghost({q: d[q]["u"][a] for q in nodes}, p, "anti", (0.0, 0.0))
+    Ucache = {}
+
+    def u_at(p, a):
+        key = (p, a)
+        if key not in Ucache:
+            Ucache[key] = U(p, a)
+        return Ucache[key]
+
+    post = {}
+    out_phip, out_qp = {}, {}
+    for p in nodes:
+        e = d[p]
+        ph, rho, F, u = phi[p], e["rho"], e["F"], e["u"]
+        dtphi = ph - phip[p]
+        alpha = (1.0 - ph) * prm["alpha_l"] + ph * prm["alpha_g"]
+        D = 0.0
+        for c, w in zip(CF[1:], WF[1:]):
+            qp_, qm_ = add(p, c), add(p, c, -1)
+            for a in range(3):
+                if c[a]:
+                    D += w * c[a] * 0.5 * (u_at(qp_, a) * P(qp_) - u_at(qm_, a) * P(qm_))
+        D /= C2F
+        T = sum(s[p]) - 0.5 * Lcp * (dtphi + D)
+        theta = (T - prm["T_sat"]) / Lcp
+        q = -(4.0 * alpha / (prm["A_coef"] * W * W)) * (prm["theta_I"] - theta) * ph * (1.0 - ph)
+        grho = [(rg - rl) * v for v in e["gr"]]
+        pfac = rg * (1.0 / rg - 1.0 / rl)
+        pr = sum(f[p]) + 0.5 * (C2F * sum(u[a] * grho[a] for a in range(3)) + rho * C2F * q * pfac)
+        nu = prm["nu_l"] * prm["nu_g"] / (ph * prm["nu_l"] + (1.0 - ph) * prm["nu_g"])
+        uu = sum(v * v for v in u)
+
+        def gamma(c, w, cs2):
+            cu = sum(c[a] * u[a] for a in range(3))
+            return w * (1.0 + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2))
+        om = 1.0 / (nu / C2F + 0.5)
+        pf = []
+        for fi, c, w in zip(f[p], CF, WF):
+            G = gamma(c, w, C2F)
+            feq = w * pr + rho * C2F * (G - w)
+            S = sum((c[a] - u[a]) * ((G - w) * C2F * grho[a] + G * F[a]) for a in range(3)) \
+                + w * rho * C2F * q * pfac
+            pf.append(fi - om * (fi - (feq - 0.5 * S)) + S)
+        omg = 1.0 / (M / C2G + 0.5)
+        oms = 1.0 / (alpha / C2G + 0.5)
+        pg, ps = [], []
+        for gi, si, c, w in zip(g[p], s[p], CG, WG):
+            G = gamma(c, w, C2G)
+            cn = sum(c[a] * e["n"][a] for a in range(3))
+            Sg = (4.0 / W) * ph * (1.0 - ph) * w * cn + w * q
+            pg.append(gi - omg * (gi - (ph * G - 0.5 * Sg)) + Sg)
+            Ss = -w * Lcp * (dtphi + D)
+            ps.append(si - oms * (si - (T * G - 0.5 * Ss)) + Ss)
+        post[p] = (pf, pg, ps)
+        out_phip[p], out_qp[p] = ph, q
+
+    def stream(k, C, W_, kind):
+        out = {}
+        opp = [C.index(tuple(-v for v in c)) for c in C]
+        for p in nodes:
+            vals = []
+            for i, c in enumerate(C):
+                src = add(p, c, -1)
+                if not (0 <= src[2] < nz):   # a z wall link reflects at the node
+                    side = 0 if src[2] < 0 else 1
+                    r = post[p][k][opp[i]]
+                    if kind == "g":
+                        r = -r + 2.0 * W_[i] * prm["phi_wall"][2][side]
+                    elif kind == "s":
+                        r = -r + 2.0 * W_[i] * prm["T_wall"][2][side]
+                    vals.append(r)
+                else:
+                    vals.append(post[(src[0] % nx, src[1] % ny, src[2])][k][i])
+            out[p] = vals
+        return out
+
+    return (stream(0, CF, WF, "f"), stream(1, CG, WG, "g"), stream(2, CG, WG, "s"), out_phip, out_qp)
+
+
+def test_bruteforce_step_equals_oracle_3d():
+    """Four steps of a 4 x 3 x 6 film (walls on z, x and y periodic) with an
+    initial velocity: the scalar 3-D step equals the oracle's populations to
+    1e-13 (mapped between the two lattice orderings by their velocities)."""
+    prm = I.film3d_params(4, nz=6)
+    prm["ny"] = 3
+    prm["gravity"] = [0.0, 0.0, -3e-3]
+    prm["body_force"] = [2e-4, -1e-4, 0.0]
+    prm["theta_I"] = 0.05
+    rng = np.random.default_rng(5)
+    z = np.arange(6) + 0.5
+    phi0 = 0.5 * (1 + np.tanh(2 * (z[:, None, None] - 2.7 + 0.4 * rng.standard_normal((1, 3, 4))) / prm["W"]))
+    phi0 = np.clip(phi0 + 0.02 * rng.standard_normal((6, 3, 4)), 0.0, 1.0)
+    T0 = 1.0 - 0.15 * z[:, None, None] + 0.05 * rng.standard_normal((6, 3, 4))
+    u0 = [1e-2 * rng.standard_normal((6, 3, 4)) for _ in range(3)]
+    Mo = Model(prm)
+    st = Mo.init(phi0, T0, u0)
+    CF, CG = _d3q19()[0], _d3q7()[0]
+    perm_f = [CF.index(tuple(int(v) for v in c)) for c in Mo.Lf.c]   # oracle index -> ours
+    perm_g = [CG.index(tuple(int(v) for v in c)) for c in Mo.Lg.c]
+    nodes = [(x, y, zz) for zz in range(6) for y in range(3) for x in range(4)]
+
+    def to_ours(pop, perm, Q):
+        a = pop.detach().numpy()
+        out = {}
+        for (x, y, zz) in nodes:
+            v = [0.0] * Q
+            for i in range(Q):
+                v[perm[i]] = float(a[i, zz, y, x])
+            out[(x, y, zz)] = v
+        return out
+    b = (to_ours(st.f, perm_f, 19), to_ours(st.g, perm_g, 7), to_ours(st.s, perm_g, 7),
+         {p: float(st.phi_prev[p[2], p[1], p[0]]) for p in nodes},
+         {p: float(st.q_prev[p[2], p[1], p[0]]) for p in nodes})
+    for n in range(4):
+        st = Mo.step(st)
+        b = brute_step_3d(prm, *b)
+        o = (to_ours(st.f, perm_f, 19), to_ours(st.g, perm_g, 7), to_ours(st.s, perm_g, 7))
+        for name, mine, ref in zip(("f", "g", "s"), b[:3], o):
+            worst = max(abs(mine[p][i] - ref[p][i]) for p in nodes for i in range(len(ref[p])))
+            scale = max(1.0, max(abs(v) for p in nodes for v in ref[p]))
+            assert worst <= 1e-13 * scale, (n, name, worst)
+        for name, mine, ref in (("phi_prev", b[3], st.phi_prev), ("q_prev", b[4], st.q_prev)):
+            worst = max(abs(mine[p] - float(ref[p[2], p[1], p[0]])) for p in nodes)
+            assert worst <= 1e-13, (n, name, worst)
+    f = Mo.fields(st)
+    assert float(f["uz"].abs().max()) > 1e-4 and float(st.q_prev.abs().max()) > 1e-5
