@@ -226,11 +226,24 @@ __device__ __forceinline__ void step2d_body(const KArgs<Real, Store>& a) {
   __shared__ Real suy[Tile2<TY>::R2Y][R2X];
   const int tiles_x = (a.nx + TX2 - 1) / TX2;
   const int ntiles = tiles_x * ((a.ny + TY - 1) / TY);
-  // XCD-aware order: hardware deals blocks to the 8 XCDs round-robin; give
-  // each XCD a contiguous band of tiles so neighbouring tiles share an L2.
+  // XCD-aware order: hardware deals blocks to the 8 XCDs round-robin.  Each
+  // XCD gets one contiguous band of tiles, so neighbouring tiles share an L2;
+  // for the 16-row tiles of grids of 32 or more tile columns each XCD takes
+  // runs of four tile rows in turn instead (FP32 4096 x 3072: 0.558 against
+  // 0.574 ms with bands; 1024 x 2048: 0.104 against 0.097 ms the other way
+  // round; the 8-row 16-bit tiles are faster with bands at both sizes).
   int t = blockIdx.x;
-  const int full = (ntiles / 8) * 8;
-  if (t < full) t = (t % 8) * (full / 8) + t / 8;
+  if (TY != 16 || tiles_x < 32) {
+    const int full = (ntiles / 8) * 8;
+    if (t < full) t = (t % 8) * (full / 8) + t / 8;
+  } else {
+    const int C = 4 * tiles_x;
+    const int full = (ntiles / (8 * C)) * (8 * C);
+    if (t < full) {
+      const int xcd = t % 8, k = t / 8;
+      t = (k / C) * (8 * C) + xcd * C + (k % C);
+    }
+  }
   const int x0 = (t % tiles_x) * TX2, y0 = (t / tiles_x) * TY;
   // interior tile: every source node of the 2-halo region (3 nodes out)
   // lies inside the domain, so no wall link and no periodic wrap occurs
