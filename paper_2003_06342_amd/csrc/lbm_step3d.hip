@@ -1,8 +1,8 @@
 // 3-D fused time step for gfx950: D3Q19 for f, D3Q7 for g and s, D3Q19
 // stencils (directional-derivative gradient and Laplacian, Sec. 3.4).
 //
-// 2.5-D blocking: a workgroup (256 lanes) owns a TX x TY column of nodes (128 x 8
-// for the FP32 step, 64 x 16 for the 16-bit step, 32 x 16 otherwise)
+// 2.5-D blocking: a workgroup (256 lanes) owns a TX x TY column of nodes (64 x 16
+// for the FP32 and 16-bit steps, 32 x 16 otherwise)
 // over a chunk of z planes and marches up z with rolling LDS rings:
 //   phase 1, plane k+2: phi = sum g_bar + q_prev/2 on the tile + 2-halo
 //                       (5-plane ring);
@@ -28,10 +28,12 @@ struct Shape3 {
   static constexpr int P2X = TX + 2, P2Y = TY + 2;   // u plane region
 };
 // 32 x 16: FP64 storage, the extended step, and the fields / diagnostics
-// pass.  128 x 8: the FP32 step (256^3 1.46 against 1.77 ms, 512^3 11.0
-// against 13.3 ms; the wider rows halve the x-halo share of the pulls).
+// pass.  64 x 16 over 32-plane chunks: the FP32 step (256^3 1.32 ms against
+// 1.35 on 128 x 8 and 1.77 on 32 x 16; 512^3 10.42 against 10.47 on 128 x
+// 8): wider rows than 32 cut the x-halo share of the pulls, and 16 rows
+// keep the y halo small.
 using ShapeStd3 = Shape3<32, 16, 32>;
-using ShapeWide3 = Shape3<128, 8, 32>;
+using ShapeWide3 = Shape3<64, 16, 32>;
 // 64 x 16 over 16-plane chunks: the 16-bit step (512^3 FP16 11.1 against
 // 12.2 ms on 32 x 16 and 11.6 on 128 x 8 with 32-plane chunks; 64-column rows
 // are whole 128-byte lines of 2-byte values; 16-plane chunks 10.77 against

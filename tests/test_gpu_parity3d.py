@@ -87,11 +87,11 @@ def test_drop3d_heat_off_f64():
 
 
 def test_film3d_f32_wide_tiles_interior():
-    """The FP32 step's 128 x 8 tiles with interior (seam-free) tiles in x and
-    y and a ragged last tile: 272 x 28 x 20, 30 steps, against the FP32
+    """The FP32 step's 64 x 16 tiles with interior (seam-free) tiles in x and
+    y and ragged last tiles: 272 x 40 x 20, 30 steps, against the FP32
     rounding floor of the oracle."""
     need_gpu()
-    prm, phi0, T0 = film3d_case(272, 28, 20, 6.0, 1.5)
+    prm, phi0, T0 = film3d_case(272, 40, 20, 6.0, 1.5)
     n = 30
     say(f"[parity3d] film3d_f32_wide: steps={n}")
     floor, ref = fp32_floor(prm, phi0, T0, n)
@@ -106,7 +106,7 @@ def test_film3d_f32_wide_tiles_interior():
 def test_film3d_full_size_256_bench_configuration():
     """The 3-D benchmark workload itself (256^3 film, seed 1, z = 32 +
     3 cos cos + noise) in the launch configuration bench.py times (FP32 on
-    128 x 8 tiles, FP64 on 32 x 16): 2 steps against the oracle, FP64 within
+    64 x 16 tiles, FP64 on 32 x 16): 2 steps against the oracle, FP64 within
     1e-10 and FP32 within 1e-5 (two steps are far from the FP32 rounding
     floor)."""
     need_gpu()
@@ -125,7 +125,7 @@ def test_film3d_full_size_256_bench_configuration():
 def test_film3d_512_compressed_workload_windows():
     """The 512^3 compressed-storage workload itself (seed 5, z = 64 + 6 cos
     cos + noise) in the launch configurations bench.py times (FP16 and BF16
-    on 64 x 16 x 16 tiles, FP32 on 128 x 8 x 32, FP64 on 32 x 16 x 32): 2 steps
+    on 64 x 16 x 16 tiles, FP32 on 64 x 16 x 32, FP64 on 32 x 16 x 32): 2 steps
     of the full grid against the oracle run on 40 x 40 column windows over
     the whole height (x and y wrapped at the window's edges), compared more
     than 11 nodes (two steps' reach) inside them; three windows, one across
