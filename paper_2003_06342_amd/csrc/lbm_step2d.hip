@@ -492,12 +492,14 @@ static hipError_t launch_step2d_t(const KArgs<Real, Store>& a, int ns, int heat,
       hipLaunchKernelGGL((k_step2d<Store, Real, NSV, HV, MV, TYV, EV, NTV, LGV>), dim3(tiles),  \
                          dim3(StepTile<TYV>::NT), 0, st, a);                                    \
   } while (0)
-// the default step with or without non-temporal stores; the extended step
-// with plain stores, on D2Q9 or D2Q5 phase-field and heat populations
-#define LBM_L(NSV, HV, MV, TYV)                                 \
-  do {                                                          \
-    if (ext && d2q5) LBM_K(NSV, HV, MV, TYV, true, false, D2Q5); \
-    else if (ext) LBM_K(NSV, HV, MV, TYV, true, false, D2Q9);   \
+// the default and the extended step with or without non-temporal stores;
+// the extended step on D2Q5 phase-field and heat populations with plain
+// stores
+#define LBM_L(NSV, HV, MV, TYV)                                      \
+  do {                                                               \
+    if (ext && d2q5) LBM_K(NSV, HV, MV, TYV, true, false, D2Q5);     \
+    else if (ext && a.nt) LBM_K(NSV, HV, MV, TYV, true, true, D2Q9); \
+    else if (ext) LBM_K(NSV, HV, MV, TYV, true, false, D2Q9);        \
     else if (a.nt) LBM_K(NSV, HV, MV, TYV, false, true, D2Q9);  \
     else LBM_K(NSV, HV, MV, TYV, false, false, D2Q9);           \
   } while (0)

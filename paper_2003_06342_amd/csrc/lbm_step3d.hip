@@ -658,14 +658,22 @@ static hipError_t launch_step3d_t(const KArgs<Real, Store>& a, int ns, int heat,
 #define LBM_K(SH, NSV, HV, MV, EV, NTV)                                                        \
   hipLaunchKernelGGL((k_step3d<SH, Store, Real, NSV, HV, MV, EV, NTV>),                         \
                      dim3(blocks3d<SH>(a.nx, a.ny, a.nz)), dim3(SH::NT), 0, st, a)
-// the step: extended (standard shape, plain stores), or the default on the
-// wide (FP32) or standard shape with or without non-temporal stores; the
-// fields pass on the standard shape
+// the step, default or extended, on the FP32 / 16-bit / FP64 shape with or
+// without non-temporal stores (the extended FP64 step with plain stores);
+// the fields pass on the standard shape
 #define LBM_L(NSV, HV, MV)                                                                   \
   do {                                                                                       \
     if constexpr (MV == MODE_STEP) {                                                         \
       if (ext) {                                                                             \
-        LBM_K(ShapeStd3, NSV, HV, MV, true, false);                                          \
+        if constexpr (kWide) {                                                               \
+          if (a.nt) LBM_K(ShapeWide3, NSV, HV, MV, true, true);                              \
+          else LBM_K(ShapeWide3, NSV, HV, MV, true, false);                                  \
+        } else if constexpr (kMid) {                                                         \
+          if (a.nt) LBM_K(ShapeMid3, NSV, HV, MV, true, true);                               \
+          else LBM_K(ShapeMid3, NSV, HV, MV, true, false);                                   \
+        } else {                                                                             \
+          LBM_K(ShapeStd3, NSV, HV, MV, true, false);                                        \
+        }                                                                                    \
       } else if constexpr (kWide) {                                                          \
         if (a.nt) LBM_K(ShapeWide3, NSV, HV, MV, false, true);                               \
         else LBM_K(ShapeWide3, NSV, HV, MV, false, false);                                   \

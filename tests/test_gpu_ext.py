@@ -125,3 +125,24 @@ def test_film3d_mrt_without_ns_f64():
     """MRT is built for the D3Q7 families (phase field and heat)."""
     prm, phi0, T0 = film3d(ns=False, **MRT)
     _check("film3d_noNS_mrt", prm, phi0, T0, 20, "f64", 1e-10)
+
+
+@pytest.mark.parametrize("variant", ["trt", "trt+biased2+div_local"])
+def test_film3d_f32(variant):
+    """The FP32 extended 3-D step runs on 64 x 16 tiles: 80 columns give one
+    full and one ragged tile in x, 20 rows one full and one ragged in y."""
+    prm, phi0, T0 = film3d(nx=80, **VARIANTS[variant])
+    nsteps = 20
+    need_gpu()
+    floor, ref = fp32_floor(prm, phi0, T0, nsteps)
+    gpu = gpu_run(prm, phi0, T0, nsteps, "f32")
+    errs = compare(gpu, ref)
+    bars = fp32_bars(floor)
+    say(f"[ext] film3d_{variant} f32: gpu {errs} | fp32 floor {floor}")
+    for k in _keys(prm):
+        assert errs[k] <= bars[k], (k, errs, floor)
+
+
+def test_film3d_f16dev_trt_biased2():
+    prm, phi0, T0 = film3d(nx=80, **VARIANTS["trt+biased2+div_local"])
+    _check("film3d_trt+biased2+div_local_f16dev", prm, phi0, T0, 20, "f16dev", 1e-3)
