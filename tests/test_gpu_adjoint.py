@@ -395,3 +395,41 @@ def test_stale_tape_and_state_guards():
     assert st == lbm.LBM_E_INVAL
     sim.sync()
     sim.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_adjoint_interior_tiles_match_oracle(storage):
+    """A grid with interior tiles (200 x 40: 64 x 8 local tiles whose pull
+    region stays inside the domain, away from the periodic seam and the
+    walls) beside seam and wall tiles; random weights on phi^N and T^N, so
+    every node's pulled-population adjoints matter.  FP64 within 1e-9, FP32
+    within the float32 floor bar."""
+    need_gpu()
+    from paper_2003_06342_amd import lbm
+    prm, phi0, T0, Tw = film(200, 40, 8.0, 1.5, g=2e-4)
+    n = 12
+    rng = np.random.default_rng(11)
+    wT = rng.standard_normal((prm["ny"], prm["nx"]))
+    wphi = rng.standard_normal((prm["ny"], prm["nx"]))
+
+    def loss(phi, T):
+        return ((torch.as_tensor(wT, dtype=T.dtype) * T[0]).sum()
+                + (torch.as_tensor(wphi, dtype=phi.dtype) * phi[0]).sum())
+    if storage == "f64":
+        ref = _oracle_grads(prm, phi0, T0, Tw, n, loss)
+        bars = {k: 1e-9 for k in ref}
+    else:
+        ref, _, bars = _f32_bar(prm, phi0, T0, Tw, n, loss)
+    say(f"[adjoint] interior tiles 200x40 {storage}, {n} steps")
+    sim = lbm.Sim(prm, storage)
+    sim.set_wall_T(1, 0, Tw)
+    sim.init(phi0, T0)
+    sim.forward_taped(n)
+    g = sim.backward(wphi, gT=wT)
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    sim.sync()
+    sim.close()
+    errs = {k: rel_l2(g[k], ref[k]) for k in ("phi0", "T0", "Tw")}
+    say(f"[adjoint] interior tiles {storage}: {errs} | bars {bars}")
+    for k, e in errs.items():
+        assert e <= bars[k], (k, errs, bars)
