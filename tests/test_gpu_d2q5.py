@@ -119,7 +119,7 @@ def test_film2d_d2q5_16bit(storage):
     ref = oracle_run(prm, phi0, T0, 100)
     errs = compare(gpu_run(prm, phi0, T0, 100, storage), ref)
     say(f"[d2q5] film2d {storage}: errors {errs}")
-    bars = ({"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 3e-3} if storage == "f16dev" else
+    bars = ({"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 1e-3} if storage == "f16dev" else
             {"phi": 1e-3, "T": 5e-3, "umag": 2e-2, "p": 5e-2})
     for k, bar in bars.items():
         assert errs[k] <= bar, (k, errs)

@@ -63,7 +63,7 @@ def test_largest_accepted_2d_grid(storage):
                 floor[k] = max(floor.get(k, 0.0), e)
     bars = {"f64": {k: 1e-10 for k in ("phi", "T", "umag", "p")},
             "f32": {k: max(1e-5, 3.0 * floor.get(k, 0.0)) for k in ("phi", "T", "umag", "p")},
-            "f16dev": {"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 3e-3}}[storage]
+            "f16dev": {"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 1e-3}}[storage]
     say(f"[maxsize] {storage}: {NX} x {ny}, {n} steps")
     sim = lbm.Sim(prm, storage)
     sim.init(phi0, T0)

@@ -99,7 +99,7 @@ def test_film3d_open_top_f64():
 def test_open_top_16bit_storage(dim):
     """Open top with FP16-deviation storage (the open face's reflected f is
     stored against f's global reference like every other slot): within the
-    16-bit bars of the closed film (phi 1e-4, T and |u| 1e-3, p 3e-3)."""
+    16-bit bars of the closed film (phi 1e-4, T, |u| and p 1e-3)."""
     if dim == 2:
         prm, phi0, T0 = film2d_open()
         n = 60
@@ -116,5 +116,5 @@ def test_open_top_16bit_storage(dim):
     ref = oracle_run(prm, phi0, T0, n)
     errs = compare(gpu_run(prm, phi0, T0, n, "f16dev"), ref)
     say(f"[open] {dim}-D open top f16dev: errors {errs}")
-    for k, bar in {"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 3e-3}.items():
+    for k, bar in {"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 1e-3}.items():
         assert errs[k] <= bar, (k, errs)

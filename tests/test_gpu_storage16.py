@@ -8,11 +8,10 @@ Measured (relative L2 after 100 steps in 2-D, 40 in 3-D): FP16 phi 7e-6 /
 per-node references took T from 5e-3 and phi from 5e-4.  BF16 is about 8x
 worse (3 fewer mantissa bits).
 
-Bars: FP16 phi, T and |u| within the 1e-3 compressed-storage target (phi
-1e-4, T and |u| 1e-3); the pressure, about its mean, is reported beside them
-(the error headline is the worst of phi, T and |u|) with a sanity bar of
-3e-3.  BF16 misses the 1e-3 target for |u| and p; its bars record the
-measured levels with margin."""
+Bars: FP16 within the 1e-3 compressed-storage target on every field (phi
+1e-4; T, |u| and p, about its mean, 1e-3).  The largest FP16 pressure error
+of the 16-bit GPU tests is 8.4e-4 (the 2-D TRT film).  BF16 misses the 1e-3
+target for |u| and p; its bars record the measured levels with margin."""
 import numpy as np
 import pytest
 
@@ -49,7 +48,7 @@ def test_deviation_storage(storage, case, steps):
     e16, e32 = compare(g16, ref), compare(g32, ref)
     say(f"[storage16] {case} {storage}: {e16} | f32 {e32}")
     assert all(np.isfinite(v) for v in e16.values())
-    bars = ({"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 3e-3} if storage == "f16dev" else
+    bars = ({"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 1e-3} if storage == "f16dev" else
             {"phi": 1e-3, "T": 5e-3, "umag": 2e-2, "p": 5e-2})
     for k, bar in bars.items():
         assert e16[k] <= bar, (k, e16)
@@ -72,7 +71,7 @@ def test_film3d_16bit_step_tiles_interior(storage):
     ref = oracle_run(prm, phi0, T0, steps)
     e16 = compare(gpu_run(prm, phi0, T0, steps, storage), ref)
     say(f"[storage16] film3d 200x56x20 {storage}: {e16}")
-    bars = ({"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 3e-3} if storage == "f16dev" else
+    bars = ({"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 1e-3} if storage == "f16dev" else
             {"phi": 1e-3, "T": 5e-3, "umag": 2e-2, "p": 5e-2})
     for k, bar in bars.items():
         assert e16[k] <= bar, (k, e16)
@@ -100,7 +99,7 @@ def test_compressed_storage_64cubed_instance_of_512cubed_run():
     for k in ("phi", "T", "umag"):
         assert errs["f16dev"][k] <= 1e-3, ("f16dev", k, errs["f16dev"])
         assert errs["bf16dev"][k] <= 2e-2, ("bf16dev", k, errs["bf16dev"])
-    assert errs["f16dev"]["p"] <= 3e-3
+    assert errs["f16dev"]["p"] <= 1e-3
     for k in ("phi", "T", "umag", "p"):
         assert errs["f32"][k] <= 1e-5, ("f32", k, errs["f32"])
 
@@ -116,7 +115,7 @@ def test_deviation_storage_full_size_bench_grid():
     n = 20
     say(f"[storage16] full size 1024x2048: oracle {n} steps")
     ref = oracle_run(prm, phi0, T0, n)
-    for storage, bars in (("f16dev", {"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 3e-3}),
+    for storage, bars in (("f16dev", {"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 1e-3}),
                           ("bf16dev", {"phi": 1e-3, "T": 5e-3, "umag": 2e-2, "p": 5e-2})):
         e = compare(gpu_run(prm, phi0, T0, n, storage), ref)
         say(f"[storage16] full size {storage}: {e}")
