@@ -347,6 +347,15 @@ def main():
                 var[name]["impl_hbm_frac"] = round(bi * rate, 4)
         for st in ("f64", "f16dev", "bf16dev"):
             record(f"film2d_1024x2048_{st}", prm, fields, st, 27, max(20, args.steps // 4), 5)
+        # the extended step options (TRT / MRT collision, biased directional
+        # derivatives, local div(u phi)): the same bytes as the default step
+        ext_opts = {"trt": dict(collision="trt", trt_lambda=[0.25, 3.0 / 16.0, 0.25]),
+                    "mrt": dict(collision="mrt", mrt_rates=[[1.1, 1.2, 1.3, 1.4]] * 3),
+                    "biased2": dict(grad_scheme="biased2"),
+                    "div_local": dict(div_local=True)}
+        for name, kw in ext_opts.items():
+            record(f"film2d_1024x2048_f32_{name}", dict(prm, **kw), fields, "f32", 27,
+                   max(20, args.steps // 4), 5)
         # second 2-D workload: the multi-mode film of Sec. 5.3 (4096 x 3072)
         for ja in (0.1, 0.025):
             pm = I.multimode_params(4096, 3072, jacob=ja)
@@ -362,6 +371,8 @@ def main():
         p3 = I.film3d_params(256)
         f3 = I.film3d_fields(p3, seed=1, h0=32.0, amp=3.0)
         record("film3d_256^3_f32", p3, f3, "f32", 33, 20, 3)
+        for name in ("trt", "biased2"):
+            record(f"film3d_256^3_f32_{name}", dict(p3, **ext_opts[name]), f3, "f32", 33, 20, 3)
         p5 = I.film3d_params(512)
         f5 = I.film3d_fields(p5, seed=5, h0=64.0, amp=6.0)
         for st in ("f32", "f16dev", "bf16dev"):
