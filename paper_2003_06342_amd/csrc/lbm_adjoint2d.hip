@@ -360,11 +360,14 @@ __global__ __launch_bounds__(TX2 * TY) void k_adj_uphi2d(const KArgs<Real, Real>
     slap[ry][rx] = L[3];
     return L[0];
   };
-  const Real lphi_u = u_at(r + 1, lx + 1, own);
-  for (int h = tid; h < RX * RY - NT; h += NT) {
-    int ry, rx;
-    halo2_rc<TY>(h, ry, rx);
-    u_at(ry, rx, false);
+  // one loop over the lane's own node (k = tid) and then its halo nodes,
+  // so that the u transpose is emitted once
+  Real lphi_u = 0;
+  for (int k = tid; k < RX * RY; k += NT) {
+    int ry = r + 1, rx = lx + 1;
+    if (k >= NT) halo2_rc<TY>(k - NT, ry, rx);
+    const Real v = u_at(ry, rx, k < NT && own);
+    if (k < NT) lphi_u = v;
   }
   __syncthreads();
   if (!own) return;
