@@ -266,7 +266,8 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--only", choices=["film3d256", "adjoint", "film2d_f16dev", "film3d512_f32",
-                                       "film3d512_f16dev", "multimode_f32", "multimode_f16dev"],
+                                       "film3d512_f16dev", "multimode_f32", "multimode_f16dev",
+                                       "film2d_ext", "film3d256_ext"],
                     help="run one secondary measurement alone (for profiling) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -298,6 +299,22 @@ def main():
         fm = I.multimode_fields(pm, seed=7)[:2]
         r = time_variant(pm, fm, st, args.steps, args.warmup)
         print(json.dumps({f"multimode_4096x3072_Ja0.1_{st}": r}), flush=True)
+        return
+    if args.only in ("film2d_ext", "film3d256_ext"):
+        # the extended step with every option at once: TRT collision, biased2
+        # directional derivatives and the local div(u phi)
+        ext = dict(collision="trt", trt_lambda=[0.25, 3.0 / 16.0, 0.25], grad_scheme="biased2",
+                   div_local=True)
+        if args.only == "film2d_ext":
+            pe = dict(I.film2d_params(1024, 2048), **ext)
+            fe = I.film2d_fields(pe, seed=0, h0=64.0, amp=4.0)[:2]
+            name = "film2d_1024x2048_f32_trt_biased2_divlocal"
+        else:
+            pe = dict(I.film3d_params(256), **ext)
+            fe = I.film3d_fields(pe, seed=1, h0=32.0, amp=3.0)
+            name = "film3d_256^3_f32_trt_biased2_divlocal"
+        r = time_variant(pe, fe, "f32", args.steps, args.warmup)
+        print(json.dumps({name: r}), flush=True)
         return
     if args.only == "film2d_f16dev":
         p2 = I.film2d_params(1024, 2048)
