@@ -3,7 +3,8 @@ anti-bounce-back, zero-gradient velocity ghost) against the FP64 oracle, in
 2-D (open top of the film; a pressure-driven channel with both x faces open
 and no-slip y walls, so corners join an open and a no-slip face) and 3-D
 (open top of the film), including an initial velocity field whose ghosts
-enter div(u phi) at the open face.  FP64 within 1e-10, FP32 within
+enter div(u phi) at the open face, and under the extended step (TRT,
+biased2 derivatives, local div(u phi)).  FP64 within 1e-10, FP32 within
 max(1e-5, 3 x the float32 floor)."""
 import numpy as np
 import pytest
@@ -118,3 +119,41 @@ def test_open_top_16bit_storage(dim):
     say(f"[open] {dim}-D open top f16dev: errors {errs}")
     for k, bar in {"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 1e-3}.items():
         assert errs[k] <= bar, (k, errs)
+
+
+EXT_ALL = dict(collision="trt", trt_lambda=[0.25, 3.0 / 16.0, 0.3], grad_scheme="biased2",
+               div_local=True)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_open_top_with_extended_step_f64(dim):
+    """The open top under the extended step (TRT collision, biased2
+    derivatives, local div(u phi)): the open face's reflected f enters the
+    TRT pairs and the biased differences read phi ghosts beyond it; FP64
+    within 1e-10."""
+    if dim == 2:
+        prm, phi0, T0 = film2d_open(**EXT_ALL)
+        _check("film2d_open_top_ext", prm, phi0, T0, 60, "f64", 1e-10)
+    else:
+        prm = I.film3d_params(80, nz=37)
+        prm["ny"] = 20
+        prm["gravity"] = [0.0, 0.0, -5e-5]
+        prm["f_open"] = [[False, False], [False, False], [False, True]]
+        prm["p_wall"] = [[0.0, 0.0], [0.0, 0.0], [0.0, 1e-4]]
+        prm.update(EXT_ALL)
+        phi0, T0 = I.film3d_fields(prm, seed=1, h0=8.0, amp=1.5, wavelength=80.0)
+        _check("film3d_open_top_ext", prm, phi0, T0, 20, "f64", 1e-10)
+
+
+def test_open_top_with_extended_step_f32():
+    """The same 2-D case with FP32 storage (64 x 16 tiles, the extended
+    kernel), within max(1e-5, 3 x the float32 floor)."""
+    prm, phi0, T0 = film2d_open(**EXT_ALL)
+    n = 60
+    need_gpu()
+    floor, ref = fp32_floor(prm, phi0, T0, n)
+    errs = compare(gpu_run(prm, phi0, T0, n, "f32"), ref)
+    bars = fp32_bars(floor)
+    say(f"[open] film2d_open_top_ext f32: {errs} | floor {floor}")
+    for k in _keys(prm):
+        assert errs[k] <= bars[k], (k, errs, floor)
