@@ -123,3 +123,29 @@ def test_film2d_d2q5_16bit(storage):
             {"phi": 1e-3, "T": 5e-3, "umag": 2e-2, "p": 5e-2})
     for k, bar in bars.items():
         assert errs[k] <= bar, (k, errs)
+
+
+def test_film2d_d2q5_open_top_trt_f64():
+    """D2Q5 g and s under an open top of f (pressure anti-bounce-back) with
+    TRT collision: the D2Q5 wall links of g and s at the top face stay
+    Dirichlet while f's reflect against the face pressure."""
+    prm, phi0, T0 = _film(collision="trt", trt_lambda=[0.25, 3.0 / 16.0, 0.3],
+                          f_open=[[False, False], [False, True], [False, False]],
+                          p_wall=[[0.0, 0.0], [0.0, 1e-4], [0.0, 0.0]])
+    _check("film2d_open_top_trt", prm, phi0, T0, 60, "f64", 1e-10)
+
+
+def test_film2d_d2q5_on_x_walls_f64():
+    """The D2Q5 film turned on its side (walls on x, periodic y): the D2Q5
+    wall links along x."""
+    prm, phi0, T0 = _film()
+    nx, ny = 70, 44
+    prm.update(nx=nx, ny=ny, bc=["wall", "periodic", "periodic"],
+               phi_wall=[[1.0, 1.0], [0.0, 0.0], [0.0, 0.0]],
+               T_wall=[[1.0, 0.0], [0.0, 0.0], [0.0, 0.0]], gravity=[-2e-5, 0.0, 0.0])
+    x = np.arange(nx) + 0.5
+    y = np.arange(ny) + 0.5
+    h = 10.0 + 1.5 * np.cos(2 * np.pi * y / ny)
+    phi0 = I.tanh_profile(h[:, None] - x[None, :], prm["W"])[None]
+    T0 = np.where(x[None, :] < h[:, None], 1.0 - x[None, :] / h[:, None], 0.0)[None]
+    _check("film2d_xwalls", prm, phi0, T0, 40, "f64", 1e-10)
