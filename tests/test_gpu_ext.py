@@ -146,3 +146,20 @@ def test_film3d_f32(variant):
 def test_film3d_f16dev_trt_biased2():
     prm, phi0, T0 = film3d(nx=80, **VARIANTS["trt+biased2+div_local"])
     _check("film3d_trt+biased2+div_local_f16dev", prm, phi0, T0, 20, "f16dev", 1e-3)
+
+
+def test_film2d_on_x_walls_f16dev():
+    """The extended step on the film turned on its side, FP16-deviation
+    storage: the 16-bit codec's wall links along x (g referenced to the
+    node's own phi beyond a wall), within 1e-3."""
+    prm, phi0, T0 = film2d(**VARIANTS["trt+biased2+div_local"])
+    nx, ny = 70, 44
+    prm.update(nx=nx, ny=ny, bc=["wall", "periodic", "periodic"],
+               phi_wall=[[1.0, 1.0], [0.0, 0.0], [0.0, 0.0]],
+               T_wall=[[1.0, 0.0], [0.0, 0.0], [0.0, 0.0]], gravity=[-2e-5, 0.0, 0.0])
+    x = np.arange(nx) + 0.5
+    y = np.arange(ny) + 0.5
+    h = 10.0 + 1.5 * np.cos(2 * np.pi * y / ny)
+    phi0 = I.tanh_profile(h[:, None] - x[None, :], prm["W"])[None]
+    T0 = np.where(x[None, :] < h[:, None], 1.0 - x[None, :] / h[:, None], 0.0)[None]
+    _check("film2d_xwalls_ext_f16dev", prm, phi0, T0, 40, "f16dev", 1e-3)

@@ -157,3 +157,28 @@ def test_open_top_with_extended_step_f32():
     say(f"[open] film2d_open_top_ext f32: {errs} | floor {floor}")
     for k in _keys(prm):
         assert errs[k] <= bars[k], (k, errs, floor)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_open_top_with_extended_step_16bit(dim):
+    """The open top under the extended step with FP16-deviation storage
+    (64 x 8 tiles in 2-D, 64 x 16 x 16 in 3-D, the extended kernels): within
+    the 16-bit bars (phi 1e-4; T, |u| and p 1e-3)."""
+    if dim == 2:
+        prm, phi0, T0 = film2d_open(**EXT_ALL)
+        n = 60
+    else:
+        prm = I.film3d_params(80, nz=37)
+        prm["ny"] = 20
+        prm["gravity"] = [0.0, 0.0, -5e-5]
+        prm["f_open"] = [[False, False], [False, False], [False, True]]
+        prm["p_wall"] = [[0.0, 0.0], [0.0, 0.0], [0.0, 1e-4]]
+        prm.update(EXT_ALL)
+        phi0, T0 = I.film3d_fields(prm, seed=1, h0=8.0, amp=1.5, wavelength=80.0)
+        n = 20
+    need_gpu()
+    say(f"[open] ext 16-bit dim={dim}: {n} steps")
+    errs = compare(gpu_run(prm, phi0, T0, n, "f16dev"), oracle_run(prm, phi0, T0, n))
+    say(f"[open] ext 16-bit dim={dim}: {errs}")
+    for k, bar in {"phi": 1e-4, "T": 1e-3, "umag": 1e-3, "p": 1e-3}.items():
+        assert errs[k] <= bar, (dim, k, errs)
