@@ -169,3 +169,32 @@ def test_film3d_512_compressed_workload_windows():
         say(f"[parity3d] 512^3 {storage}: worst window errors {worst}")
         for k in ("phi", "T", "umag", "p"):
             assert worst[k] <= tol, (storage, k, worst)
+
+
+@pytest.mark.parametrize("storage,ext", [("f32", False), ("f16dev", False), ("f32", True),
+                                         ("f16dev", True)])
+def test_checkpoint_resume_bitwise_3d(storage, ext):
+    """get_state / set_state round trip in 3-D (64 x 16 tile shapes; for
+    16-bit storage the blob carries the per-node temperature reference), for
+    the default and the extended step (TRT, biased2, local div(u phi)): a run
+    resumed from the blob equals the uninterrupted run bit for bit."""
+    need_gpu()
+    from paper_2003_06342_amd import lbm
+    prm, phi0, T0 = film3d_case(80, 20, 37, 8.0, 1.5)
+    if ext:
+        prm.update(collision="trt", trt_lambda=[0.25, 3.0 / 16.0, 0.3], grad_scheme="biased2",
+                   div_local=True)
+    say(f"[parity3d] checkpoint {storage} ext={ext}")
+    a = lbm.Sim(prm, storage).init(phi0, T0)
+    a.step(7)
+    blob = a.get_state()
+    a.step(6)
+    fa = {k: v.cpu().numpy() for k, v in a.fields().items()}
+    a.close()
+    b = lbm.Sim(prm, storage)
+    b.set_state(blob)
+    b.step(6)
+    fb = {k: v.cpu().numpy() for k, v in b.fields().items()}
+    b.close()
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
