@@ -198,3 +198,24 @@ def test_checkpoint_resume_bitwise_3d(storage, ext):
     b.close()
     for k in fa:
         assert np.array_equal(fa[k], fb[k]), k
+
+
+def test_check_every_reports_unstable_3d():
+    """check_every > 0 in 3-D: a NaN in the initial phase field makes the
+    first check return LBM_E_UNSTABLE with the step count at that check; a
+    healthy run with checks equals the same run without them bit for bit."""
+    need_gpu()
+    from paper_2003_06342_amd import lbm
+    prm, phi0, T0 = film3d_case(36, 20, 21, 6.0, 1.5)
+    ref = gpu_run(prm, phi0, T0, 9, "f32")
+    chk = gpu_run(dict(prm, check_every=4), phi0, T0, 9, "f32")
+    for k in ("phi", "T", "ux", "uz", "p"):
+        assert np.array_equal(ref[k], chk[k]), k
+    bad = phi0.copy()
+    bad[10, 8, 12] = np.nan
+    sim = lbm.Sim(dict(prm, check_every=2), "f32").init(bad, T0)
+    with pytest.raises(lbm.LBMError) as e:
+        sim.step(8)
+    assert e.value.status == lbm.LBM_E_UNSTABLE
+    assert sim.steps_taken == 2
+    sim.close()
