@@ -219,3 +219,38 @@ def test_check_every_reports_unstable_3d():
     assert e.value.status == lbm.LBM_E_UNSTABLE
     assert sim.steps_taken == 2
     sim.close()
+
+
+def test_film3d_initial_velocity_and_pressure_f64():
+    """A 3-D film started from a non-zero velocity field (all three
+    components) and a pressure field: the initial equilibria and sources
+    (with div(u phi) of the initial u) against the oracle's, FP64 within
+    1e-10 after 15 steps."""
+    need_gpu()
+    prm, phi0, T0 = film3d_case(36, 20, 21, 6.0, 1.5)
+    nz, ny, nx = phi0.shape
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    z = (np.arange(nz) + 0.5) / nz
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    wall = np.sin(np.pi * Z)          # vanishes at both z walls
+    u0 = [1e-3 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y) * wall,
+          1e-3 * np.cos(2 * np.pi * X) * np.sin(2 * np.pi * Y) * wall,
+          5e-4 * np.sin(2 * np.pi * X) * wall]
+    p0 = 1e-4 * np.cos(2 * np.pi * Y) * wall
+    say("[parity3d] initial u and p, 36x20x21, 15 steps")
+    ref = oracle_run(prm, phi0, T0, 15, u0=u0, p0=p0)
+    gpu = gpu_run(prm, phi0, T0, 15, "f64", u0=u0, p0=p0)
+    errs = compare(gpu, ref)
+    say(f"[parity3d] initial u and p: {errs}")
+    for k in ("phi", "T", "umag", "p"):
+        assert errs[k] <= 1e-10, (k, errs)
+
+
+def test_split_steps_equal_one_call_3d():
+    need_gpu()
+    prm, phi0, T0 = film3d_case(36, 20, 21, 6.0, 1.5)
+    one = gpu_run(prm, phi0, T0, 12, "f32")
+    many = gpu_run(prm, phi0, T0, 12, "f32", chunks=[1, 4, 7])
+    for k in ("phi", "T", "ux", "uy", "uz", "p"):
+        assert np.array_equal(one[k], many[k]), k
