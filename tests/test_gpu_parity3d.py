@@ -254,3 +254,29 @@ def test_split_steps_equal_one_call_3d():
     many = gpu_run(prm, phi0, T0, 12, "f32", chunks=[1, 4, 7])
     for k in ("phi", "T", "ux", "uy", "uz", "p"):
         assert np.array_equal(one[k], many[k]), k
+
+
+@pytest.mark.parametrize("nx,ny,nz,bcz", [(1, 1, 6, "periodic"), (1, 1, 2, "wall"),
+                                           (3, 2, 2, "wall"), (5, 3, 4, "wall"),
+                                           (2, 5, 3, "periodic")])
+def test_degenerate_tiny_grids_3d(nx, ny, nz, bcz):
+    """3-D grids far below one tile: single periodic columns in x and y, the
+    smallest walled z axis (two planes, so the 2-plane ghost mirrors the far
+    plane) and a fully periodic box, against the oracle in FP64 (within
+    1e-12 of the field scale) and FP32 (1e-5); step(0) is a no-op."""
+    need_gpu()
+    prm = I.film3d_params(4, nz=4)
+    prm["nx"], prm["ny"], prm["nz"] = nx, ny, nz
+    prm["bc"] = ["periodic", "periodic", bcz]
+    rng = np.random.default_rng(1)
+    phi0 = 0.5 + 0.3 * rng.standard_normal((nz, ny, nx)).clip(-1, 1)
+    T0 = 0.5 + 0.1 * rng.standard_normal((nz, ny, nx))
+    say(f"[parity3d] tiny grid {nx}x{ny}x{nz} bcz={bcz}")
+    g0 = gpu_run(prm, phi0, T0, 0, "f64")
+    assert np.abs(g0["phi"] - phi0).max() < 1e-14
+    ref = oracle_run(prm, phi0, T0, 5)
+    for storage, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        gpu = gpu_run(prm, phi0, T0, 5, storage)
+        for k in ("phi", "T", "ux", "uy", "uz", "p"):
+            err = np.abs(gpu[k] - ref[k]).max()
+            assert err <= tol * max(1.0, np.abs(ref[k]).max()), (storage, k, err)
