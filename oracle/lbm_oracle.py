@@ -88,8 +88,12 @@ same ones):
       biased difference would break (sum_i w_i [phi(x + c_i) - phi(x)] is a
       Laplacian).  Ghosts two nodes beyond a wall mirror the second node
       (R13).
-Parity unpinned beyond self-consistency and invariants: R6-R10, R13 as
-modelling choices, and chaotic trajectories after pinch-off.
+Pinned readings beyond the closed forms: R8 (the Fourier symbol of the
+central stencil on u_a phi, and second-order convergence of the wall rows),
+R9 (linear ramps and the planar interface) and R13 (manufactured ghosts,
+hand-computed edges).  Parity unpinned beyond self-consistency and
+invariants: R6, R7 and R10 as modelling choices, and chaotic trajectories
+after pinch-off.
 """
 from __future__ import annotations
 

@@ -16,8 +16,13 @@
   above 10 eps, and a tail deviation below phi* = eps W / 4, the level at
   which the regularised counter flux vanishes.
 
+* R8, div(u phi) as the central stencil of Eq. Grad on each u_a phi: its
+  Fourier symbol sin(k) on a periodic lattice (D2Q9 and D3Q19), exact for a
+  product of two modes.
+
 Each pin comes with a planted mistake in a subclass of the oracle (a flipped
-ghost sign, a swapped axis order) that the same check rejects.
+ghost sign, a swapped axis order, the product rule in place of the stencil
+on the product) that the same check rejects.
 """
 import math
 
@@ -297,3 +302,78 @@ def test_planar_interface_with_regularised_normal():
         assert tail < eps * W / 4, (W, tail)
     assert core[0] / core[1] > 3 and core[1] / core[2] > 3, core
     assert core[2] < 5e-4, core
+
+
+# ---------------------------------------------------------------------------
+# R8: div(u phi) is the central stencil of Eq. Grad applied to each product
+# u_a phi.  On a periodic lattice the stencil's Fourier symbol along an axis
+# is sin(k) for every isotropic lattice (sum_i w_i c_ia^2 = c_s^2): it maps
+# sin(k x) to sin(k) cos(k x).  With u_x = U cos(k2 x) and phi = sin(k1 x),
+# u_x phi = U/2 [sin((k1 + k2) x) + sin((k1 - k2) x)], so the oracle's
+# divergence must equal U/2 [sin(k1 + k2) cos((k1 + k2) x) + sin(k1 - k2)
+# cos((k1 - k2) x)] exactly (round-off), in 2-D (D2Q9) and 3-D (D3Q19).
+# ---------------------------------------------------------------------------
+
+def _periodic_model(dim, n, cls=Model):
+    if dim == 2:
+        p = I.base_params(dim=2, nx=n, ny=6, ns=True, heat=True)
+        p["bc"] = ["periodic", "periodic", "periodic"]
+    else:
+        p = I.base_params(dim=3, nx=n, ny=5, nz=4, ns=True, heat=True, lat_f="D3Q19",
+                          lat_g="D3Q7", lat_s="D3Q7")
+        p["bc"] = ["periodic", "periodic", "periodic"]
+    return cls(p)
+
+
+def _symbol_case(M, n, axis):
+    """u along `axis` = U cos(k2 s), phi = sin(k1 s) with s the coordinate on
+    that axis; returns the oracle's div(u phi) and the closed form."""
+    shape = M.shape
+    k1, k2, U = 2 * np.pi * 3 / n, 2 * np.pi * 5 / n, 0.02
+    s = np.arange(n, dtype=np.float64)
+    bshape = [1, 1, 1]
+    bshape[2 - axis] = n
+    phi = np.broadcast_to(np.sin(k1 * s).reshape(bshape), shape).copy()
+    ua = np.broadcast_to((U * np.cos(k2 * s)).reshape(bshape), shape).copy()
+    u = [torch.zeros(shape, dtype=F64) for _ in range(3)]
+    u[axis] = torch.tensor(ua)
+    D = M.divergence(u, M.ghost_pad(torch.tensor(phi), "phi")).numpy()
+    ex = 0.5 * U * (np.sin(k1 + k2) * np.cos((k1 + k2) * s)
+                    + np.sin(k1 - k2) * np.cos((k1 - k2) * s))
+    return D, np.broadcast_to(ex.reshape(bshape), shape)
+
+
+@pytest.mark.parametrize("dim,axis", [(2, 0), (2, 1), (3, 0), (3, 2)])
+def test_divergence_fourier_symbol(dim, axis):
+    n = 24
+    M = _periodic_model(dim, n)
+    if axis == 1 and dim == 2:
+        # the y axis of the 2-D model has 6 nodes: use a square grid instead
+        p = dict(M.prm, nx=n, ny=n)
+        M = Model(p)
+    if axis == 2:
+        p = dict(M.prm, nz=n)
+        M = Model(p)
+    D, ex = _symbol_case(M, n, axis)
+    assert np.abs(D - ex).max() < 1e-15
+    assert np.abs(ex).max() > 1e-3
+
+
+class _ProductRuleDivergence(Model):
+    """Planted mistake: div(u phi) as u . grad(phi) + phi div(u), each with
+    the central stencil (equal in the continuum, not on the lattice)."""
+
+    def divergence(self, u, phi_padded):
+        gphi = self.grad(phi_padded)
+        phi = phi_padded[1:-1, 1:-1, 1:-1]
+        D = torch.zeros(self.shape, dtype=self.dt)
+        for a in range(3):
+            D = D + u[a] * gphi[a] + phi * self.grad(self.ghost_pad(u[a], "anti"))[a]
+        return D
+
+
+def test_divergence_symbol_rejects_product_rule():
+    n = 24
+    M = _periodic_model(2, n, _ProductRuleDivergence)
+    D, ex = _symbol_case(M, n, 0)
+    assert np.abs(D - ex).max() > 1e-4
