@@ -19,10 +19,12 @@
 * R8, div(u phi) as the central stencil of Eq. Grad on each u_a phi: its
   Fourier symbol sin(k) on a periodic lattice (D2Q9 and D3Q19), exact for a
   product of two modes.
+* R10, the linear interpolation of alpha(phi): the steady series
+  conduction across a static interface between walls at T = 1 and T = 0.
 
 Each pin comes with a planted mistake in a subclass of the oracle (a flipped
 ghost sign, a swapped axis order, the product rule in place of the stencil
-on the product) that the same check rejects.
+on the product, a harmonic alpha) that the same check rejects.
 """
 import math
 
@@ -377,3 +379,47 @@ def test_divergence_symbol_rejects_product_rule():
     M = _periodic_model(2, n, _ProductRuleDivergence)
     D, ex = _symbol_case(M, n, 0)
     assert np.abs(D - ex).max() > 1e-4
+
+
+# ---------------------------------------------------------------------------
+# R10: alpha(phi) = (1 - phi) alpha_l + phi alpha_g.  A static interface
+# (heat only: no flow, no phase change) across a column between walls at
+# T = 1 and T = 0 conducts in series.  With alpha constant over each node's
+# unit cell, the continuum steady state of (alpha T')' = 0 is linear in
+# each cell with slope proportional to 1 / alpha_i; at the node centre
+#   T_i = 1 - (sum_{j<i} 1/alpha_j + 1/(2 alpha_i)) / sum_j 1/alpha_j.
+# The oracle's steady state follows it for the linear interpolation, and a
+# harmonic interpolation (the form of Eq. Viscosity) misses it by 6e-2.
+# ---------------------------------------------------------------------------
+
+class _HarmonicDiffusivity(Model):
+    """Planted mistake: alpha interpolated harmonically."""
+
+    def diffusivity(self, phi):
+        al, ag = self.prm["alpha_l"], self.prm["alpha_g"]
+        return al * ag / (phi * al + (1.0 - phi) * ag)
+
+
+def _layered_column(cls, ny=16, al=0.05, ag=0.25, W=4.0, nsteps=2000):
+    p = I.base_params(dim=2, nx=1, ny=ny, ns=False, heat=True, phase_change=False,
+                      alpha_l=al, alpha_g=ag, W=W)
+    p["bc"] = ["periodic", "wall", "periodic"]
+    p["phi_wall"] = [[0.0, 0.0], [0.0, 1.0], [0.0, 0.0]]
+    p["T_wall"] = [[0.0, 0.0], [1.0, 0.0], [0.0, 0.0]]
+    M = cls(p)
+    y = np.arange(ny) + 0.5
+    st = M.init(I.tanh_profile(y - ny / 2, W)[None, :, None], (1.0 - y / ny)[None, :, None])
+    f = M.fields(M.run(st, nsteps))
+    phi = f["phi"][0, :, 0].numpy()
+    r = 1.0 / ((1.0 - phi) * al + phi * ag)
+    R = np.concatenate([[0.0], np.cumsum(r)])
+    T_series = 1.0 - 0.5 * (R[:-1] + R[1:]) / R[-1]
+    return np.abs(f["T"][0, :, 0].numpy() - T_series).max()
+
+
+def test_layered_conduction_follows_linear_diffusivity():
+    assert _layered_column(Model) < 1e-3
+
+
+def test_layered_conduction_rejects_harmonic_diffusivity():
+    assert _layered_column(_HarmonicDiffusivity) > 1e-2
