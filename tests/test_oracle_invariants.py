@@ -1,7 +1,7 @@
 """Oracle pins on exact discrete invariants: init round trip (R12), mass
 conservation without sources (P6), the enthalpy invariant that fixes the
-heat-source sign (P7), z-invariance 3-D == 2-D (P13) and the buoyancy sign
-(R5)."""
+heat-source sign (P7) and the backward time derivative (R7), z-invariance
+3-D == 2-D (P13) and the buoyancy sign (R5)."""
 import numpy as np
 import pytest
 import torch
@@ -122,3 +122,29 @@ def test_buoyant_bubble_rises():
     f = M.fields(st)
     assert yc(f["phi"]) > y0 + 0.05
     assert float(f["uy"][0].max()) > 0
+
+
+def test_enthalpy_invariant_pins_the_backward_time_derivative():
+    """R7: the invariant of P7 holds because dphi/dt is the backward
+    difference phi^n - phi^{n-1} with phi^{n-1} advanced every step.  A lag
+    that is not advanced (phi_prev kept at phi^0) breaks it."""
+    from oracle.lbm_oracle import State
+
+    class StaleLag(Model):
+        def step(self, st, u_prescribed=None):
+            new = super().step(st, u_prescribed)
+            return State(new.f, new.g, new.s, st.phi_prev, new.q_prev)
+
+    p = I.base_params(dim=2, nx=16, ny=12, **I.FB)
+    p["gravity"] = [0.0, -1e-4, 0.0]
+    phi0, T0 = I.random_smooth_fields(p, seed=11, T_amp=0.5)
+    drift = {}
+    for name, cls in (("backward", Model), ("stale", StaleLag)):
+        M = cls(p)
+        st = M.init(phi0, T0)
+        E0 = M.diagnostics(st)["enthalpy"]
+        st = M.run(st, 20)
+        drift[name] = abs(M.diagnostics(st)["enthalpy"] - E0)
+    scale = float(np.abs(T0).sum() + p["L_over_cp"] * np.abs(phi0).sum())
+    assert drift["backward"] / scale < 1e-13
+    assert drift["stale"] / scale > 1e-8, drift
