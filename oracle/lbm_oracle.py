@@ -92,9 +92,10 @@ Pinned readings beyond the closed forms: R8 (the Fourier symbol of the
 central stencil on u_a phi, and second-order convergence of the wall rows),
 R9 (linear ramps and the planar interface), R10 (steady series conduction
 across a static interface), R7 (the enthalpy invariant, which a lag that is
-not advanced breaks) and R13 (manufactured ghosts, hand-computed edges).
-Parity unpinned beyond self-consistency and invariants: R6 as a modelling
-choice, and chaotic trajectories after pinch-off.
+not advanced breaks), R6 (the exact discrete mass balance of the lagged
+production) and R13 (manufactured ghosts, hand-computed edges).  Parity
+unpinned beyond self-consistency and invariants: chaotic trajectories after
+pinch-off.
 """
 from __future__ import annotations
 

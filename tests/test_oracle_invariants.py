@@ -1,7 +1,8 @@
 """Oracle pins on exact discrete invariants: init round trip (R12), mass
 conservation without sources (P6), the enthalpy invariant that fixes the
-heat-source sign (P7) and the backward time derivative (R7), z-invariance
-3-D == 2-D (P13) and the buoyancy sign (R5)."""
+heat-source sign (P7) and the backward time derivative (R7), the discrete
+mass balance of the lagged production (R6), z-invariance 3-D == 2-D (P13)
+and the buoyancy sign (R5)."""
 import numpy as np
 import pytest
 import torch
@@ -148,3 +149,43 @@ def test_enthalpy_invariant_pins_the_backward_time_derivative():
     scale = float(np.abs(T0).sum() + p["L_over_cp"] * np.abs(phi0).sum())
     assert drift["backward"] / scale < 1e-13
     assert drift["stale"] / scale > 1e-8, drift
+
+
+def _mass_balance_residual(p, cls, nsteps=10):
+    """Largest |Phi^{n+1} - Phi^n - [(3 - w)/2 Q^n + (w - 1)/2 Q^{n-1}]| over
+    the run, relative to max |Q^n| (Phi = sum phi, Q = sum q over the
+    periodic domain, w the BGK rate of g)."""
+    M = cls(p)
+    st = M.init(*I.random_smooth_fields(p, seed=11, T_amp=0.5))
+    w = 1.0 / (3.0 * p["mobility"] + 0.5)
+    Phi, Q, Qp = [], [], []
+    for _ in range(nsteps):
+        m = M.macros(st)
+        Phi.append(float(m.phi.sum()))
+        Q.append(float(m.q.sum()))
+        Qp.append(float(st.q_prev.sum()))
+        st = M.step(st)
+    Phi, Q, Qp = map(np.array, (Phi, Q, Qp))
+    pred = 0.5 * (3.0 - w) * Q[:-1] + 0.5 * (w - 1.0) * Qp[:-1]
+    return np.abs(np.diff(Phi) - pred).max() / np.abs(Q).max()
+
+
+@pytest.mark.parametrize("mobility", [0.0816, 0.02])
+def test_mass_balance_pins_the_lagged_production(mobility):
+    """R6: phi = sum g + q^{n-1}/2 (the production lagged one step).  Summed
+    over a periodic domain, the BGK collision of g with its production
+    source P^g_i = w_i q gives the exact discrete balance
+        Phi^{n+1} - Phi^n = (3 - w)/2 Q^n + (w - 1)/2 Q^{n-1},
+    weights summing to one (no production is lost), with w = 1/(3 M + 1/2).
+    It holds to round-off at two mobilities; dropping the lag term from the
+    phi moment breaks it."""
+    p = I.base_params(dim=2, nx=16, ny=12, **dict(I.FB, mobility=mobility))
+    p["gravity"] = [0.0, -1e-4, 0.0]
+    assert _mass_balance_residual(p, Model) < 1e-11
+
+    class NoLag(Model):
+        def macros(self, st, u_prescribed=None):
+            from oracle.lbm_oracle import State
+            st0 = State(st.f, st.g, st.s, st.phi_prev, torch.zeros_like(st.q_prev))
+            return super().macros(st0, u_prescribed)
+    assert _mass_balance_residual(p, NoLag) > 1e-3
